@@ -1,0 +1,167 @@
+/*
+ * g3pcf: anisotropic three-point correlation function multipoles on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * For every primary galaxy i the library gathers its secondaries j within
+ * R_max, rotates each separation into the line-of-sight frame of i, bins it
+ * into one of nbins equal-width radial shells and accumulates
+ *
+ *     a^{(i)}_{lm}(b) = sum_{j in shell b} w_j conj(Y_lm(u_ij))
+ *
+ * through sums of monomials of the unit separation (paper: Sec. 3.1 and its
+ * eq. 1; Algorithm 1), converts the monomial sums to spherical-harmonic
+ * coefficients in FP64, and reduces
+ *
+ *     zeta^m_{l l'}(b1, b2) = sum_i w_i a^{(i)}_{lm}(b1) conj(a^{(i)}_{l'm}(b2))
+ *
+ * over all primaries (the per-primary product a_lm(r1) a*_l'm(r2) of Sec. 3.1,
+ * summed over primaries as the expansion zeta = sum zeta^m_{ll'} Y_lm Y*_l'm
+ * requires).  The projection uses conj(Y_lm) so that zeta is the coefficient
+ * of Y_lm(r1) Y*_l'm(r2) in that expansion.  Y_lm is orthonormal with the
+ * Condon-Shortley phase (zeta does not depend on the phase convention).
+ *
+ * Conventions shared by every entry point
+ *   - Every pointer is a DEVICE pointer unless its comment says HOST.
+ *   - The caller owns all memory.  The library keeps no allocation between
+ *     calls; scratch lives in the caller's workspace `ws`.
+ *   - Arguments are validated synchronously, before anything is enqueued; an
+ *     invalid call returns a negative g3pcf_status and enqueues nothing.
+ *   - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL is the
+ *     default stream).  The call returns without synchronising unless
+ *     `pairs_out` is set.
+ *   - Calls are reentrant given distinct workspaces.  Two calls that share a
+ *     workspace must be ordered on one stream.
+ *   - g3pcf_last_error() returns a thread-local message for the last non-OK
+ *     return on the calling thread.
+ */
+#ifndef G3PCF_H
+#define G3PCF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  G3PCF_OK = 0,
+  G3PCF_EINVAL = -1,       /* an argument is out of range or inconsistent     */
+  G3PCF_EWORKSPACE = -2,   /* ws is NULL or smaller than g3pcf_workspace_bytes */
+  G3PCF_EHIP = -3,         /* a HIP runtime call or kernel launch failed       */
+  G3PCF_EUNSUPPORTED = -4  /* valid request this build does not implement      */
+} g3pcf_status;
+
+typedef enum {
+  G3PCF_LOS_Z = 0,        /* line of sight = box z axis for every primary      */
+  G3PCF_LOS_OBSERVER = 1  /* line of sight from `observer` through the primary;
+                             each separation is rotated so that this line maps
+                             to +z (Sec. 3.1, Fig. 2)                           */
+} g3pcf_los;
+
+typedef enum {
+  G3PCF_PREC_FP64 = 0,    /* plain FP64 throughout                             */
+  G3PCF_PREC_FP32 = 1,    /* pair stage: FP32 accumulation; zeta stage: FP32 MFMA */
+  G3PCF_PREC_BF16X3 = 2   /* zeta stage only: each FP32 operand split into three
+                             bfloat16 terms, the six products with i+j <= 2 on
+                             BF16 MFMA with FP32 accumulation                   */
+} g3pcf_prec;
+
+typedef enum { G3PCF_F32 = 0, G3PCF_F64 = 1 } g3pcf_dtype;
+
+typedef enum {
+  G3PCF_BASIS_CARTESIAN = 0, /* the paper's monomials (dx/r)^k (dy/r)^p (dz/r)^q,
+                                k+p+q <= 10: 286 sums per shell (eq. 1)          */
+  G3PCF_BASIS_SPIN = 1       /* (dx/r - i dy/r)^m (dz/r)^n, m+n <= 10: 121 real
+                                sums per shell; the same zeta with fewer FMAs    */
+} g3pcf_basis;
+
+typedef struct {
+  int64_t n;               /* number of galaxies, 0 <= n < 2^31                  */
+  const void* pos;         /* [n][3] row-major positions, dtype pos_dtype         */
+  g3pcf_dtype pos_dtype;
+  const double* w;         /* [n] weights                                         */
+  double box[3];           /* box side lengths; > 0                              */
+  double box_lo[3];        /* low corner of the box                              */
+  int periodic;            /* 1: minimum-image separations, positions are wrapped
+                              into [box_lo, box_lo + box); needs rmax <= box/2.
+                              0: positions should lie in the box (points outside
+                              are still handled exactly, only more slowly)       */
+  double observer[3];      /* read only when los == G3PCF_LOS_OBSERVER           */
+  double rmax;             /* outer radius R_max > 0; pairs with 0 < r < R_max   */
+  int nbins;               /* 1..32 equal-width shells [b dr, (b+1) dr), dr = R_max/nbins */
+  int lmax;                /* 0..10                                              */
+  g3pcf_los los;
+  g3pcf_prec pair_prec;    /* G3PCF_PREC_FP64 or G3PCF_PREC_FP32                 */
+  g3pcf_prec zeta_prec;    /* G3PCF_PREC_FP64, _FP32 or _BF16X3; the sum over
+                              blocks of primaries is always FP64                 */
+  g3pcf_basis basis;
+  const uint8_t* primary_mask; /* [n] nonzero = primary, or NULL (all galaxies are
+                              primaries); secondaries are always all n galaxies  */
+  int accumulate;          /* 0: overwrite the outputs; 1: add into them         */
+  int64_t* pairs_out;      /* HOST pointer or NULL.  If set, the call waits for
+                              the stream and stores the number of accepted
+                              ordered (primary, secondary) pairs                 */
+} g3pcf_problem;
+
+/* Number of doubles in zeta for (lmax, nbins): (lmax+1)^3 * nbins^2 * 2.
+ * Layout [m][l][l'][b1][b2][re, im]; entries with l < m or l' < m are zero.
+ * zeta^{-m} = conj(zeta^m) is not stored. */
+size_t g3pcf_zeta_len(int lmax, int nbins);
+
+/* Monomial sums accumulated per (primary, shell) by the pair stage:
+ * 286 for the cartesian basis (the paper's count (l+1)(l+2)(l+3)/6 at
+ * l = 10, vectorisation section), 121 for the spin basis.  The kernels always
+ * accumulate to degree 10; lmax only selects which coefficients are kept.
+ * Returns -1 for an unknown basis. */
+int g3pcf_num_terms(int basis);
+
+/* Bytes of device workspace needed by g3pcf_forward (backward = 0) or
+ * g3pcf_backward (backward = 1) for this problem.  Depends only on the
+ * problem's sizes and settings, never on the data.  Returns G3PCF_OK and stores
+ * the size in *bytes, or a negative status. */
+int g3pcf_workspace_bytes(const g3pcf_problem* prob, int backward, size_t* bytes);
+
+/* Forward pass.  zeta: [g3pcf_zeta_len] doubles (device).  ws: device
+ * workspace of at least g3pcf_workspace_bytes(prob, 0) bytes, 256-byte aligned.
+ * Steps: wrap positions and build a cell list (counting sort); for every
+ * primary gather its secondaries, rotate, bin and accumulate monomial sums on
+ * the pair kernel; convert them to a_lm in FP64; reduce zeta per block of
+ * primaries as a Gram product A^H W A on MFMA; add the block into zeta in FP64.
+ * Errors: G3PCF_EINVAL, G3PCF_EWORKSPACE, G3PCF_EHIP (message in
+ * g3pcf_last_error).  On error the contents of zeta are unspecified. */
+int g3pcf_forward(const g3pcf_problem* prob, double* zeta, void* ws, size_t ws_bytes,
+                  void* stream);
+
+/* Adjoint pass.  With L = sum over the real view of grad_zeta * zeta
+ * (grad_zeta laid out like zeta), stores dL/dw_k for every galaxy k in
+ * grad_w [n] (added to it when accumulate = 1).  zeta is linear in the weight
+ * of a primary and quadratic in the weight of a secondary:
+ *   primary term   dL/dw_i = Re sum conj(G) a_lm(b1) conj(a_l'm(b2)),
+ *   secondary term dL/dw_k += w_i Re sum_lm conj(Y_lm(u_ik)) H_lm(b_ik)
+ * with G = grad_re + i grad_im and H_lm(b) = U_lm(b) + conj(V_lm(b)),
+ *   U_lm(b)  = sum_{l',b2} conj(G^m_{ll'}(b, b2)) conj(a_l'm(b2)),
+ *   V_l'm(b) = sum_{l,b1}  conj(G^m_{ll'}(b1, b)) a_lm(b1).
+ * The a_lm are recomputed from the pairs, not stored by the forward pass.
+ * Position gradients are not provided.  ws: at least
+ * g3pcf_workspace_bytes(prob, 1) bytes.  Same errors as g3pcf_forward. */
+int g3pcf_backward(const g3pcf_problem* prob, const double* grad_zeta, double* grad_w,
+                   void* ws, size_t ws_bytes, void* stream);
+
+/* Message for the last non-OK return on this thread ("" if none). */
+const char* g3pcf_last_error(void);
+
+/* Diagnostic, host only, no device use: evaluates the library's own
+ * monomial-sum -> a_lm conversion (the same coefficient table the pair kernels
+ * use) for a single unit vector u with unit weight, i.e. conj(Y_lm(u)) as the
+ * pair stage represents it.  out: HOST array of (lmax+1)(lmax+2) doubles,
+ * (re, im) pairs in triangular order (l(l+1)/2 + m), 0 <= m <= l <= lmax.
+ * Returns G3PCF_OK or G3PCF_EINVAL (unknown basis, lmax outside 0..10, NULL). */
+int g3pcf_conj_ylm_via_monomials(int basis, int lmax, double ux, double uy, double uz,
+                                 double* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* G3PCF_H */

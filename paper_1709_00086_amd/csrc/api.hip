@@ -1,0 +1,356 @@
+// C ABI of libg3pcf: argument validation, workspace layout and the order of
+// the stages on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <set>
+#include <string>
+#include <utility>
+
+#include "internal.h"
+
+namespace g3 {
+namespace {
+
+thread_local std::string t_err;
+
+int fail(int code, const std::string& msg) {
+  t_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  return fail(G3PCF_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+constexpr size_t kAlign = 256;
+size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Ws {
+  size_t pos4, tmp4, cid, perm, tmp_perm, wsort, cell_start, cell_count, flags, plist, scan,
+      counters, scratch, A, C, ops, gcoef, gsort;
+  size_t scan_bytes;
+  size_t total;
+  int64_t PB;   // primaries per pair-block
+  int S;        // scratch entries per wave
+  int Kp;       // padded rows of a zeta sub-block (bf16 operands)
+  Grid grid;
+  RowLayout lay;
+};
+
+Ws plan(const g3pcf_problem& p, int backward) {
+  Ws w{};
+  const int64_t n = p.n;
+  const int fp64 = (p.pair_prec == G3PCF_PREC_FP64);
+  const size_t rb = fp64 ? 32 : 16;
+  w.grid = make_grid(p);
+  w.lay = make_layout(p.lmax, p.nbins);
+  const int64_t ncell = w.grid.ncell;
+  w.PB = std::max<int64_t>(1, std::min<int64_t>(n, backward ? 16384 : kPairBlockMax));
+  w.S = int(std::min<int64_t>(kScratchMax, std::max<int64_t>(64, (n + 63) / 64 * 64)));
+  w.Kp = ((std::min<int64_t>(kZetaBlock, w.PB) + 31) / 32) * 32;
+  w.scan_bytes = scan_tmp_bytes(std::max<int64_t>(ncell + 1, n + 1));
+  size_t at = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = at;
+    at += up(std::max<size_t>(bytes, 1));
+    return o;
+  };
+  w.pos4 = take(size_t(n) * rb);
+  w.tmp4 = take(size_t(n) * rb);
+  w.cid = take(size_t(n) * 4);
+  w.perm = take(size_t(n) * 4);
+  w.tmp_perm = take(size_t(n) * 4);
+  w.wsort = take(size_t(n) * 8);
+  w.cell_start = take(size_t(ncell + 1) * 4);
+  w.cell_count = take(size_t(ncell + 1) * 4);
+  w.flags = take(size_t(2 * (n + 1)) * 4);
+  w.plist = take(size_t(n) * 4);
+  w.scan = take(w.scan_bytes);
+  w.counters = take(256);
+  w.scratch = take(size_t(kPairWaves) * w.S * 4);
+  w.A = take(size_t(w.PB) * w.lay.W * 8);
+  w.C = take(size_t(kZetaSplitK) * sum_wm2(w.lay) * 8);
+  w.ops = (!backward && p.zeta_prec == G3PCF_PREC_BF16X3) ? take(size_t(6) * w.lay.W * w.Kp * 2)
+                                                           : take(0);
+  if (backward) {
+    const int T = (p.basis == G3PCF_BASIS_SPIN) ? kTermsSpin : kTermsCart;
+    w.gcoef = take(size_t(w.PB) * p.nbins * T * 8);
+    w.gsort = take(size_t(n) * 8);
+  }
+  w.total = at;
+  return w;
+}
+
+bool finite3(const double* v) {
+  return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]);
+}
+
+int validate(const g3pcf_problem* p) {
+  if (!p) return fail(G3PCF_EINVAL, "problem is NULL");
+  if (p->n < 0 || p->n >= (int64_t(1) << 31) - 64)
+    return fail(G3PCF_EINVAL, "n must satisfy 0 <= n < 2^31 - 64");
+  if (p->n > 0 && (!p->pos || !p->w)) return fail(G3PCF_EINVAL, "pos and w must be non-NULL");
+  if (p->pos_dtype != G3PCF_F32 && p->pos_dtype != G3PCF_F64)
+    return fail(G3PCF_EINVAL, "pos_dtype must be G3PCF_F32 or G3PCF_F64");
+  if (!finite3(p->box) || !finite3(p->box_lo) || p->box[0] <= 0 || p->box[1] <= 0 ||
+      p->box[2] <= 0)
+    return fail(G3PCF_EINVAL, "box must be finite and positive, box_lo finite");
+  if (!(p->rmax > 0) || !std::isfinite(p->rmax)) return fail(G3PCF_EINVAL, "rmax must be > 0");
+  if (p->periodic) {
+    const double mn = std::min(p->box[0], std::min(p->box[1], p->box[2]));
+    if (p->rmax > 0.5 * mn)
+      return fail(G3PCF_EINVAL, "periodic box needs rmax <= min(box) / 2");
+  }
+  if (p->nbins < 1 || p->nbins > kMaxBins) return fail(G3PCF_EINVAL, "nbins must be 1..32");
+  if (p->lmax < 0 || p->lmax > kDeg) return fail(G3PCF_EINVAL, "lmax must be 0..10");
+  if (p->los != G3PCF_LOS_Z && p->los != G3PCF_LOS_OBSERVER)
+    return fail(G3PCF_EINVAL, "los must be G3PCF_LOS_Z or G3PCF_LOS_OBSERVER");
+  if (p->los == G3PCF_LOS_OBSERVER && !finite3(p->observer))
+    return fail(G3PCF_EINVAL, "observer must be finite");
+  if (p->pair_prec != G3PCF_PREC_FP64 && p->pair_prec != G3PCF_PREC_FP32)
+    return fail(G3PCF_EINVAL, "pair_prec must be G3PCF_PREC_FP64 or G3PCF_PREC_FP32");
+  if (p->zeta_prec != G3PCF_PREC_FP64 && p->zeta_prec != G3PCF_PREC_FP32 &&
+      p->zeta_prec != G3PCF_PREC_BF16X3)
+    return fail(G3PCF_EINVAL, "zeta_prec must be FP64, FP32 or BF16X3");
+  if (p->basis != G3PCF_BASIS_CARTESIAN && p->basis != G3PCF_BASIS_SPIN)
+    return fail(G3PCF_EINVAL, "basis must be G3PCF_BASIS_CARTESIAN or G3PCF_BASIS_SPIN");
+  if (p->accumulate != 0 && p->accumulate != 1)
+    return fail(G3PCF_EINVAL, "accumulate must be 0 or 1");
+  return G3PCF_OK;
+}
+
+std::mutex g_tab_mu;
+std::set<std::pair<int, int>> g_tab_done;
+
+int ensure_tables(int basis) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_tab_mu);
+  if (g_tab_done.count({dev, basis})) return G3PCF_OK;
+  e = upload_tables(basis);
+  if (e != hipSuccess) return hip_fail(e, "conversion table upload");
+  g_tab_done.insert({dev, basis});
+  return G3PCF_OK;
+}
+
+template <typename T>
+T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+struct Counters {
+  long long nprim;
+  unsigned long long pairs;
+  unsigned long long pairs_adj;
+  int queue;
+};
+
+// Stages shared by forward and backward: cell list and primary list.
+int stage_catalogue(const g3pcf_problem& p, const Ws& w, void* ws, hipStream_t st) {
+  const int fp64 = (p.pair_prec == G3PCF_PREC_FP64);
+  hipError_t e = launch_cells(p, w.grid, at<void>(ws, w.pos4), at<int>(ws, w.cell_start),
+                              at<int>(ws, w.cell_count), at<int>(ws, w.cid), at<int>(ws, w.perm),
+                              at<double>(ws, w.wsort), at<void>(ws, w.tmp4),
+                              at<int>(ws, w.tmp_perm), nullptr, at<void>(ws, w.scan),
+                              w.scan_bytes, fp64, st);
+  if (e != hipSuccess) return hip_fail(e, "cell list");
+  Counters* c = at<Counters>(ws, w.counters);
+  e = launch_fill_int(reinterpret_cast<int*>(c), sizeof(Counters) / 4, 0, st);
+  if (e != hipSuccess) return hip_fail(e, "counters");
+  e = launch_primaries(p.primary_mask, at<int>(ws, w.perm), p.n, at<int>(ws, w.flags),
+                       at<int>(ws, w.plist), &c->nprim, at<void>(ws, w.scan), w.scan_bytes, st);
+  if (e != hipSuccess) return hip_fail(e, "primary list");
+  return G3PCF_OK;
+}
+
+PairArgs pair_args(const g3pcf_problem& p, const Ws& w, void* ws) {
+  PairArgs a{};
+  Counters* c = at<Counters>(ws, w.counters);
+  a.pos4 = at<void>(ws, w.pos4);
+  a.cell_start = at<int>(ws, w.cell_start);
+  a.plist = at<int>(ws, w.plist);
+  a.nprim = &c->nprim;
+  a.scratch = at<int>(ws, w.scratch);
+  a.scratch_per_wave = w.S;
+  a.queue = &c->queue;
+  a.pairs = &c->pairs;
+  for (int k = 0; k < 3; ++k) {
+    a.nc[k] = w.grid.nc[k];
+    a.s[k] = w.grid.s[k];
+    a.inv_s[k] = w.grid.inv_s[k];
+    a.lo[k] = w.grid.lo[k];
+    a.L[k] = w.grid.L[k];
+    a.tight[k] = w.grid.tight[k];
+    a.obs[k] = p.observer[k];
+  }
+  a.periodic = w.grid.periodic;
+  a.rmax = p.rmax;
+  a.rmax_search = w.grid.rsearch;
+  a.nbins = p.nbins;
+  a.lmax = p.lmax;
+  a.los = p.los;
+  a.A = at<double>(ws, w.A);
+  a.lay = w.lay;
+  a.perm = at<int>(ws, w.perm);
+  a.wsort = at<double>(ws, w.wsort);
+  return a;
+}
+
+int finish_pairs(const g3pcf_problem& p, const Ws& w, void* ws, hipStream_t st) {
+  if (!p.pairs_out) return G3PCF_OK;
+  unsigned long long host = 0;
+  hipError_t e = hipMemcpyAsync(&host, &at<Counters>(ws, w.counters)->pairs, sizeof(host),
+                                hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "pair count read-back");
+  *p.pairs_out = (int64_t)host;
+  return G3PCF_OK;
+}
+
+}  // namespace
+}  // namespace g3
+
+using namespace g3;
+
+extern "C" {
+
+size_t g3pcf_zeta_len(int lmax, int nbins) {
+  if (lmax < 0 || nbins < 1) return 0;
+  const size_t L1 = size_t(lmax) + 1;
+  return L1 * L1 * L1 * size_t(nbins) * size_t(nbins) * 2;
+}
+
+int g3pcf_num_terms(int basis) {
+  if (basis == G3PCF_BASIS_CARTESIAN) return kTermsCart;
+  if (basis == G3PCF_BASIS_SPIN) return kTermsSpin;
+  return -1;
+}
+
+const char* g3pcf_last_error(void) { return t_err.c_str(); }
+
+int g3pcf_workspace_bytes(const g3pcf_problem* prob, int backward, size_t* bytes) {
+  int rc = validate(prob);
+  if (rc) return rc;
+  if (!bytes) return fail(G3PCF_EINVAL, "bytes is NULL");
+  if (backward != 0 && backward != 1) return fail(G3PCF_EINVAL, "backward must be 0 or 1");
+  *bytes = plan(*prob, backward).total;
+  return G3PCF_OK;
+}
+
+int g3pcf_forward(const g3pcf_problem* prob, double* zeta, void* ws, size_t ws_bytes,
+                  void* stream) {
+  int rc = validate(prob);
+  if (rc) return rc;
+  if (!zeta) return fail(G3PCF_EINVAL, "zeta is NULL");
+  const g3pcf_problem& p = *prob;
+  const Ws w = plan(p, 0);
+  if (!ws || ws_bytes < w.total)
+    return fail(G3PCF_EWORKSPACE, "workspace needs " + std::to_string(w.total) + " bytes");
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign)
+    return fail(G3PCF_EWORKSPACE, "workspace must be 256-byte aligned");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((rc = ensure_tables(p.basis))) return rc;
+  const size_t zlen = g3pcf_zeta_len(p.lmax, p.nbins);
+  hipError_t e;
+  if (!p.accumulate && (e = launch_fill_double(zeta, int64_t(zlen), 0.0, st)) != hipSuccess)
+    return hip_fail(e, "zeta clear");
+  if (p.n == 0) {
+    if (p.pairs_out) *p.pairs_out = 0;
+    return G3PCF_OK;
+  }
+  if ((rc = stage_catalogue(p, w, ws, st))) return rc;
+  PairArgs a = pair_args(p, w, ws);
+  const int fp64 = (p.pair_prec == G3PCF_PREC_FP64);
+  Counters* c = at<Counters>(ws, w.counters);
+  for (int64_t b0 = 0; b0 < p.n; b0 += w.PB) {
+    a.p_begin = b0;
+    a.p_count = std::min<int64_t>(w.PB, p.n - b0);
+    if ((e = launch_pair_forward(a, fp64, p.basis, st)) != hipSuccess)
+      return hip_fail(e, "pair kernel");
+    for (int64_t s0 = 0; s0 < a.p_count; s0 += kZetaBlock) {
+      ZetaArgs z{};
+      z.A = a.A;
+      z.wsort = a.wsort;
+      z.plist = a.plist;
+      z.nprim = &c->nprim;
+      z.row_begin = b0;
+      z.sub_begin = s0;
+      z.K = int(std::min<int64_t>(kZetaBlock, a.p_count - s0));
+      z.lay = w.lay;
+      z.ops = at<void>(ws, w.ops);
+      z.C32 = at<float>(ws, w.C);
+      z.C64 = at<double>(ws, w.C);
+      z.zeta = zeta;
+      z.prec = p.zeta_prec;
+      if ((e = launch_zeta_block(z, st)) != hipSuccess) return hip_fail(e, "zeta block");
+    }
+  }
+  return finish_pairs(p, w, ws, st);
+}
+
+int g3pcf_backward(const g3pcf_problem* prob, const double* grad_zeta, double* grad_w, void* ws,
+                   size_t ws_bytes, void* stream) {
+  int rc = validate(prob);
+  if (rc) return rc;
+  if (!grad_zeta || (!grad_w && prob->n > 0))
+    return fail(G3PCF_EINVAL, "grad_zeta and grad_w must be non-NULL");
+  const g3pcf_problem& p = *prob;
+  const Ws w = plan(p, 1);
+  if (!ws || ws_bytes < w.total)
+    return fail(G3PCF_EWORKSPACE, "workspace needs " + std::to_string(w.total) + " bytes");
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign)
+    return fail(G3PCF_EWORKSPACE, "workspace must be 256-byte aligned");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((rc = ensure_tables(p.basis))) return rc;
+  if (p.n == 0) {
+    if (p.pairs_out) *p.pairs_out = 0;
+    return G3PCF_OK;
+  }
+  hipError_t e;
+  if ((rc = stage_catalogue(p, w, ws, st))) return rc;
+  double* gsort = at<double>(ws, w.gsort);
+  if ((e = launch_fill_double(gsort, p.n, 0.0, st)) != hipSuccess)
+    return hip_fail(e, "gradient clear");
+  PairArgs a = pair_args(p, w, ws);
+  const int fp64 = (p.pair_prec == G3PCF_PREC_FP64);
+  Counters* c = at<Counters>(ws, w.counters);
+  const ConvTable* tab = nullptr;
+  if ((e = conv_table_device(p.basis, &tab)) != hipSuccess) return hip_fail(e, "table address");
+  a.gcoef = at<double>(ws, w.gcoef);
+  a.grad_w = gsort;
+  for (int64_t b0 = 0; b0 < p.n; b0 += w.PB) {
+    a.p_begin = b0;
+    a.p_count = std::min<int64_t>(w.PB, p.n - b0);
+    a.pairs = &c->pairs;
+    if ((e = launch_pair_forward(a, fp64, p.basis, st)) != hipSuccess)
+      return hip_fail(e, "pair kernel (recompute)");
+    AdjArgs j{};
+    j.A = a.A;
+    j.gz = grad_zeta;
+    j.wsort = a.wsort;
+    j.plist = a.plist;
+    j.perm = a.perm;
+    j.nprim = &c->nprim;
+    j.p_begin = b0;
+    j.p_count = a.p_count;
+    j.lay = w.lay;
+    j.basis = p.basis;
+    j.table = tab;
+    j.gcoef = at<double>(ws, w.gcoef);
+    j.grad_w = gsort;
+    if ((e = launch_adj_coef(j, st)) != hipSuccess) return hip_fail(e, "adjoint coefficients");
+    a.pairs = &c->pairs_adj;
+    if ((e = launch_pair_adjoint(a, fp64, p.basis, st)) != hipSuccess)
+      return hip_fail(e, "pair adjoint kernel");
+  }
+  if ((e = launch_unpermute(gsort, a.perm, p.n, p.accumulate, grad_w, st)) != hipSuccess)
+    return hip_fail(e, "gradient permute");
+  return finish_pairs(p, w, ws, st);
+}
+
+}  // extern "C"

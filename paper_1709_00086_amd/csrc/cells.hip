@@ -1,0 +1,350 @@
+// Catalogue staging: wrap, cell assignment, counting sort into cell order,
+// deterministic order inside every cell, and the compacted primary list.
+//
+// The paper keeps its galaxies in a node-local k-d tree for the range search
+// (Algorithm 1, "search node-local k-d tree").  On the GPU a uniform cell grid
+// sorted by a counting sort serves the same purpose: every (cy, cz) row of
+// cells is one contiguous run of galaxies in memory, so the pair kernels read
+// candidates with coalesced loads.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "internal.h"
+
+namespace g3 {
+
+namespace {
+
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 4;  // per thread
+constexpr int kScanTile = kScanBlock * kScanItems;
+
+__device__ inline double wrap_coord(double x, double lo, double L) {
+  double t = fmod(x - lo, L);
+  if (t < 0.0) t += L;
+  if (t >= L) t = 0.0;
+  return lo + t;
+}
+
+template <typename Real>
+struct Vec4;
+template <>
+struct Vec4<float> {
+  using T = float4;
+};
+template <>
+struct Vec4<double> {
+  using T = double4;
+};
+
+struct GridDev {
+  int nc[3];
+  double inv_s[3], lo[3], L[3];
+  int periodic;
+};
+
+__device__ inline int cell_axis(double x, double lo, double inv_s, int nc) {
+  double f = floor((x - lo) * inv_s);
+  int c = (f < 0.0) ? 0 : (f >= double(nc) ? nc - 1 : int(f));
+  return c;
+}
+
+// Wrap (periodic), convert to the compute precision and assign a cell.
+template <typename Real, typename In>
+__global__ void k_assign(const In* __restrict__ pos, const double* __restrict__ w, int64_t n,
+                         GridDev g, typename Vec4<Real>::T* __restrict__ out4,
+                         int* __restrict__ cid, int* __restrict__ count) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double x[3];
+  for (int a = 0; a < 3; ++a) {
+    double v = double(pos[3 * i + a]);
+    if (g.periodic) {
+      v = wrap_coord(v, g.lo[a], g.L[a]);
+      Real r = Real(v);
+      // a float that rounds up onto the upper box edge wraps to the lower edge
+      if (double(r) >= g.lo[a] + g.L[a]) r = Real(g.lo[a]);
+      v = double(r);
+    } else {
+      v = double(Real(v));
+    }
+    x[a] = v;
+  }
+  const int cx = cell_axis(x[0], g.lo[0], g.inv_s[0], g.nc[0]);
+  const int cy = cell_axis(x[1], g.lo[1], g.inv_s[1], g.nc[1]);
+  const int cz = cell_axis(x[2], g.lo[2], g.inv_s[2], g.nc[2]);
+  const int c = (cz * g.nc[1] + cy) * g.nc[0] + cx;
+  typename Vec4<Real>::T v4;
+  v4.x = Real(x[0]);
+  v4.y = Real(x[1]);
+  v4.z = Real(x[2]);
+  v4.w = Real(w[i]);
+  out4[i] = v4;
+  cid[i] = c;
+  atomicAdd(&count[c], 1);
+}
+
+template <typename V4>
+__global__ void k_scatter(const V4* __restrict__ in4, const int* __restrict__ cid, int64_t n,
+                          const int* __restrict__ cell_start, int* __restrict__ cursor,
+                          V4* __restrict__ out4, int* __restrict__ out_perm) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = cid[i];
+  const int slot = cell_start[c] + atomicAdd(&cursor[c], 1);
+  out4[slot] = in4[i];
+  out_perm[slot] = int(i);
+}
+
+// One wave per cell: order the members by original index so the whole
+// pipeline is deterministic (the scatter's atomics are not).
+template <typename V4>
+__global__ void k_cell_order(const V4* __restrict__ in4, const int* __restrict__ in_perm,
+                             const int* __restrict__ cell_start, int64_t ncell,
+                             const double* __restrict__ w, V4* __restrict__ out4,
+                             int* __restrict__ perm, double* __restrict__ wsort) {
+  const int64_t c = int64_t(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  if (c >= ncell) return;
+  const int s0 = cell_start[c], s1 = cell_start[c + 1];
+  for (int a = s0 + lane; a < s1; a += kWave) {
+    const int pa = in_perm[a];
+    int rank = 0;
+    for (int b = s0; b < s1; ++b) rank += (in_perm[b] < pa) ? 1 : 0;
+    const int dst = s0 + rank;
+    out4[dst] = in4[a];
+    perm[dst] = pa;
+    wsort[dst] = w[pa];
+  }
+}
+
+__global__ void k_primary_flags(const uint8_t* __restrict__ mask, const int* __restrict__ perm,
+                                int64_t n, int* __restrict__ flags) {
+  const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (s > n) return;
+  if (s == n) {
+    flags[s] = 0;
+    return;
+  }
+  flags[s] = (mask == nullptr || mask[perm[s]] != 0) ? 1 : 0;
+}
+
+__global__ void k_primary_list(const int* __restrict__ flags, const int* __restrict__ pos,
+                               int64_t n, int* __restrict__ plist,
+                               long long* __restrict__ nprim) {
+  const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (s > n) return;
+  if (s == n) {
+    *nprim = pos[n];
+    return;
+  }
+  if (flags[s]) plist[pos[s]] = int(s);
+}
+
+__global__ void k_fill_int(int* p, int64_t count, int value) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = value;
+}
+
+__global__ void k_fill_double(double* p, int64_t count, double value) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = value;
+}
+
+// ---- exclusive scan of int32 (three phases, recursive over tile sums) ----
+__global__ void k_scan_tiles(const int* __restrict__ in, int* __restrict__ out, int64_t count,
+                             int* __restrict__ tile_sums) {
+  __shared__ int sh[kScanBlock];
+  const int64_t base = int64_t(blockIdx.x) * kScanTile + threadIdx.x * kScanItems;
+  int v[kScanItems];
+  int s = 0;
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t i = base + k;
+    v[k] = (i < count) ? in[i] : 0;
+    s += v[k];
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < kScanBlock; off <<= 1) {
+    int t = (threadIdx.x >= off) ? sh[threadIdx.x - off] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += t;
+    __syncthreads();
+  }
+  int run = sh[threadIdx.x] - s;  // exclusive prefix of this thread
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t i = base + k;
+    if (i < count) out[i] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == kScanBlock - 1) tile_sums[blockIdx.x] = sh[threadIdx.x];
+}
+
+__global__ void k_scan_add(int* __restrict__ out, int64_t count,
+                           const int* __restrict__ tile_offsets) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < count) out[i] += tile_offsets[i / kScanTile];
+}
+
+inline unsigned blocks_for(int64_t n, int bs) { return unsigned((n + bs - 1) / bs); }
+
+}  // namespace
+
+size_t scan_tmp_bytes(int64_t count) {
+  size_t total = 0;
+  int64_t c = count;
+  while (c > 1) {
+    const int64_t tiles = (c + kScanTile - 1) / kScanTile;
+    total += size_t(2 * tiles + 64) * sizeof(int);
+    c = tiles;
+  }
+  return total + 256;
+}
+
+hipError_t launch_scan(const int* in, int* out, int64_t count, void* tmp, size_t tmp_bytes,
+                       hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  const int64_t tiles = (count + kScanTile - 1) / kScanTile;
+  int* sums = static_cast<int*>(tmp);
+  int* offs = sums + tiles + 32;
+  hipLaunchKernelGGL(k_scan_tiles, dim3(unsigned(tiles)), dim3(kScanBlock), 0, st, in, out,
+                     count, sums);
+  if (tiles > 1) {
+    const size_t used = size_t(2 * tiles + 64) * sizeof(int);
+    hipError_t e = launch_scan(sums, offs, tiles, static_cast<char*>(tmp) + used,
+                               tmp_bytes - used, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scan_add, dim3(blocks_for(count, 256)), dim3(256), 0, st, out, count,
+                       offs);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_int(int* p, int64_t count, int value, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_int, dim3(blocks_for(count, 256)), dim3(256), 0, st, p, count,
+                     value);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_double(double* p, int64_t count, double value, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_double, dim3(blocks_for(count, 256)), dim3(256), 0, st, p, count,
+                     value);
+  return hipGetLastError();
+}
+
+Grid make_grid(const g3pcf_problem& p) {
+  Grid g{};
+  g.periodic = p.periodic ? 1 : 0;
+  // Margin so that every candidate the FP32 acceptance test can accept is
+  // visited: positions carry about 1e-7 relative rounding.
+  double ext = 0.0;
+  for (int a = 0; a < 3; ++a)
+    ext = std::max(ext, std::fabs(p.box_lo[a]) + std::fabs(p.box[a]));
+  g.rsearch = p.rmax * (1.0 + 1e-5) + 1e-6 * ext + 1e-9;
+  // Cells of about R_max / 4: a row (cy, cz) of cells is a contiguous run of
+  // galaxies, and the search window spans about nine cells per axis.
+  const double target = p.rmax / 4.0;
+  int64_t cap = std::max<int64_t>(64, 4 * p.n);
+  cap = std::min<int64_t>(cap, int64_t(1) << 24);
+  for (int a = 0; a < 3; ++a) {
+    g.lo[a] = p.box_lo[a];
+    g.L[a] = p.box[a];
+    double nc = std::floor(p.box[a] / target);
+    nc = std::max(1.0, std::min(nc, 1024.0));
+    g.nc[a] = int(nc);
+  }
+  while (int64_t(g.nc[0]) * g.nc[1] * g.nc[2] > cap) {
+    for (int a = 0; a < 3; ++a) g.nc[a] = std::max(1, (g.nc[a] * 4) / 5);
+  }
+  for (int a = 0; a < 3; ++a) {
+    g.s[a] = g.L[a] / g.nc[a];
+    g.inv_s[a] = double(g.nc[a]) / g.L[a];
+    // periodic axis where [x - R, x + R] can touch more than nc cells
+    g.tight[a] = (g.periodic && (2.0 * g.rsearch + 2.0 * g.s[a] >= g.L[a])) ? 1 : 0;
+  }
+  g.ncell = int64_t(g.nc[0]) * g.nc[1] * g.nc[2];
+  return g;
+}
+
+hipError_t launch_cells(const g3pcf_problem& p, const Grid& g, void* pos4, int* cell_start,
+                        int* cell_count, int* cid, int* perm, double* wsort, void* tmp4,
+                        int* tmp_perm, double* /*tmp_w*/, void* scan_tmp,
+                        size_t scan_tmp_bytes_, int fp64, hipStream_t st) {
+  const int64_t n = p.n;
+  GridDev gd;
+  for (int a = 0; a < 3; ++a) {
+    gd.nc[a] = g.nc[a];
+    gd.inv_s[a] = g.inv_s[a];
+    gd.lo[a] = g.lo[a];
+    gd.L[a] = g.L[a];
+  }
+  gd.periodic = g.periodic;
+  hipError_t e = launch_fill_int(cell_count, g.ncell + 1, 0, st);
+  if (e != hipSuccess) return e;
+  const unsigned nb = blocks_for(n, 256);
+  // pos4 holds the staged (original order) values first; the final sorted
+  // values end up in pos4 as well, with tmp4 as the intermediate.
+  if (fp64) {
+    if (p.pos_dtype == G3PCF_F64)
+      hipLaunchKernelGGL((k_assign<double, double>), dim3(nb), dim3(256), 0, st,
+                         static_cast<const double*>(p.pos), p.w, n, gd,
+                         static_cast<double4*>(pos4), cid, cell_count);
+    else
+      hipLaunchKernelGGL((k_assign<double, float>), dim3(nb), dim3(256), 0, st,
+                         static_cast<const float*>(p.pos), p.w, n, gd,
+                         static_cast<double4*>(pos4), cid, cell_count);
+  } else {
+    if (p.pos_dtype == G3PCF_F64)
+      hipLaunchKernelGGL((k_assign<float, double>), dim3(nb), dim3(256), 0, st,
+                         static_cast<const double*>(p.pos), p.w, n, gd,
+                         static_cast<float4*>(pos4), cid, cell_count);
+    else
+      hipLaunchKernelGGL((k_assign<float, float>), dim3(nb), dim3(256), 0, st,
+                         static_cast<const float*>(p.pos), p.w, n, gd,
+                         static_cast<float4*>(pos4), cid, cell_count);
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // cell_start = exclusive scan of the counts (ncell + 1 entries, last = n)
+  if ((e = launch_scan(cell_count, cell_start, g.ncell + 1, scan_tmp, scan_tmp_bytes_, st)) !=
+      hipSuccess)
+    return e;
+  if ((e = launch_fill_int(cell_count, g.ncell + 1, 0, st)) != hipSuccess) return e;
+  const unsigned nbc = blocks_for(g.ncell, 256 / kWave);
+  if (fp64) {
+    hipLaunchKernelGGL((k_scatter<double4>), dim3(nb), dim3(256), 0, st,
+                       static_cast<const double4*>(pos4), cid, n, cell_start, cell_count,
+                       static_cast<double4*>(tmp4), tmp_perm);
+    hipLaunchKernelGGL((k_cell_order<double4>), dim3(nbc), dim3(256), 0, st,
+                       static_cast<const double4*>(tmp4), tmp_perm, cell_start, g.ncell, p.w,
+                       static_cast<double4*>(pos4), perm, wsort);
+  } else {
+    hipLaunchKernelGGL((k_scatter<float4>), dim3(nb), dim3(256), 0, st,
+                       static_cast<const float4*>(pos4), cid, n, cell_start, cell_count,
+                       static_cast<float4*>(tmp4), tmp_perm);
+    hipLaunchKernelGGL((k_cell_order<float4>), dim3(nbc), dim3(256), 0, st,
+                       static_cast<const float4*>(tmp4), tmp_perm, cell_start, g.ncell, p.w,
+                       static_cast<float4*>(pos4), perm, wsort);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_primaries(const uint8_t* mask, const int* perm, int64_t n, int* flags,
+                            int* plist, long long* nprim, void* scan_tmp,
+                            size_t scan_tmp_bytes_, hipStream_t st) {
+  const unsigned nb = blocks_for(n + 1, 256);
+  hipLaunchKernelGGL(k_primary_flags, dim3(nb), dim3(256), 0, st, mask, perm, n, flags);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // positions: exclusive scan into flags + (n + 1)
+  int* pos = flags + (n + 1);
+  if ((e = launch_scan(flags, pos, n + 1, scan_tmp, scan_tmp_bytes_, st)) != hipSuccess)
+    return e;
+  hipLaunchKernelGGL(k_primary_list, dim3(nb), dim3(256), 0, st, flags, pos, n, plist, nprim);
+  return hipGetLastError();
+}
+
+}  // namespace g3

@@ -1,0 +1,167 @@
+// Internal declarations shared by the g3pcf HIP sources (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/g3pcf.h"
+
+namespace g3 {
+
+// The pair kernels always accumulate monomials up to this total degree; a
+// smaller lmax only drops coefficients at conversion time.
+constexpr int kDeg = 10;
+constexpr int kTermsCart = (kDeg + 1) * (kDeg + 2) * (kDeg + 3) / 6;  // 286
+constexpr int kTermsSpin = (kDeg + 1) * (kDeg + 1);                   // 121 real sums
+constexpr int kMaxBins = 32;
+constexpr int kWave = 64;
+constexpr int kOutPerBin = (kDeg + 1) * (kDeg + 1);  // real a_lm outputs per shell (121)
+
+// Rows of A (primaries) reduced per Gram product on MFMA.
+constexpr int kZetaBlock = 4096;
+// Split-K slices of the Gram product (partials summed in order in FP64).
+constexpr int kZetaSplitK = 4;
+// Persistent waves of the pair kernel.
+constexpr int kPairWaves = 4096;
+// Maximum pair-block (primaries whose a_lm rows are held at once).
+constexpr int kPairBlockMax = 131072;
+// Per-wave scratch (neighbour indices) upper bound.
+constexpr int kScratchMax = 1 << 16;
+
+// Sparse monomial -> a_lm conversion table, one row per real output of a
+// shell.  Output o = (m, part, l) with part 0 = Re, 1 = Im (m >= 1 only).
+struct ConvTable {
+  int nout;            // 121
+  int nnz;
+  short out_m[kOutPerBin], out_l[kOutPerBin], out_part[kOutPerBin];
+  int rowptr[kOutPerBin + 1];
+  short term[4096];
+  double coef[4096];
+  // the same entries grouped by monomial term (for the adjoint)
+  int trowptr[kTermsCart + 1];
+  short tout[4096];
+  double tcoef[4096];
+};
+
+// Host: build the conversion table for a basis (0 cartesian, 1 spin).
+void build_conv_table(int basis, ConvTable* t);
+
+// Cell grid of the sorted catalogue.
+struct Grid {
+  double rsearch;      // search radius: R_max plus a margin for FP32 rounding
+  int nc[3];
+  double s[3], inv_s[3];
+  double lo[3], L[3];
+  int periodic;
+  int tight[3];        // periodic axis where the search window can exceed the box
+  int64_t ncell;
+};
+
+Grid make_grid(const g3pcf_problem& p);
+
+// Layout of one shell's real outputs inside an A row.
+struct RowLayout {
+  int lmax, nb;
+  int W;               // total row width
+  int off[kDeg + 2];   // column offset of each m block
+  int d[kDeg + 1];     // (lmax + 1 - m) * nb
+  int wm[kDeg + 1];    // block width: d for m = 0, 2d for m >= 1
+};
+
+RowLayout make_layout(int lmax, int nb);
+
+// Arguments of the pair kernels (forward accumulation and adjoint scatter).
+struct PairArgs {
+  const void* pos4;          // [n] (x, y, z, w) in cell order, float4 or double4
+  const int* cell_start;     // [ncell + 1]
+  const int* plist;          // [*nprim] primary slots in cell order
+  const long long* nprim;    // device scalar: number of primaries
+  int* scratch;              // per-wave neighbour lists
+  int scratch_per_wave;
+  int* queue;                // device scalar: next primary (relative to p_begin)
+  unsigned long long* pairs; // device scalar: accepted pairs
+  long long p_begin;         // first primary of this pair-block
+  long long p_count;         // primaries in this pair-block (upper bound)
+  // geometry (double, used for the candidate search)
+  int nc[3];
+  double s[3], inv_s[3], lo[3], L[3];
+  int periodic;
+  int tight[3];
+  double rmax, rmax_search;
+  int nbins;
+  int lmax;
+  int los;                   // 0 z, 1 observer
+  double obs[3];
+  // outputs
+  double* A;                 // [p_count][W] a_lm rows (forward)
+  RowLayout lay;
+  // adjoint
+  const double* gcoef;       // [p_count][nbins][T] monomial-space adjoint coefficients
+  const int* perm;           // [n] slot -> original index
+  double* grad_w;            // [n] original order
+  const double* wsort;       // [n] weights in cell order (FP64)
+};
+
+// ---- launchers (each returns hipGetLastError after the launch) ----
+hipError_t launch_cells(const g3pcf_problem& p, const Grid& g, void* pos4, int* cell_start,
+                        int* cell_count, int* cid, int* perm, double* wsort, void* tmp4,
+                        int* tmp_perm, double* tmp_w, void* scan_tmp, size_t scan_tmp_bytes,
+                        int fp64, hipStream_t st);
+hipError_t launch_primaries(const uint8_t* mask, const int* perm, int64_t n, int* flags,
+                            int* plist, long long* nprim, void* scan_tmp,
+                            size_t scan_tmp_bytes, hipStream_t st);
+hipError_t launch_fill_int(int* p, int64_t count, int value, hipStream_t st);
+hipError_t launch_fill_double(double* p, int64_t count, double value, hipStream_t st);
+hipError_t launch_pair_forward(const PairArgs& a, int fp64, int basis, hipStream_t st);
+hipError_t launch_pair_adjoint(const PairArgs& a, int fp64, int basis, hipStream_t st);
+hipError_t upload_tables(int basis);
+
+struct ZetaArgs {
+  const double* A;           // [rows][W]
+  const double* wsort;       // weights in cell order
+  const int* plist;
+  const long long* nprim;
+  long long row_begin;       // global primary index of A row 0
+  long long sub_begin;       // first row of this sub-block (relative to A)
+  int K;                     // rows in this sub-block (upper bound)
+  RowLayout lay;
+  void* ops;                 // bf16 split operands
+  float* C32;                // [splitK][sum W_m^2] partial Gram (FP32 / BF16X3)
+  double* C64;               // [splitK][sum W_m^2] partial Gram (FP64)
+  double* zeta;
+  int prec;
+};
+hipError_t launch_zeta_block(const ZetaArgs& z, hipStream_t st);
+
+// Adjoint helpers
+struct AdjArgs {
+  const double* A;           // [rows][W]
+  const double* gz;          // grad_zeta
+  const double* wsort;
+  const int* plist;
+  const int* perm;
+  const long long* nprim;
+  long long p_begin;
+  long long p_count;
+  RowLayout lay;
+  int basis;
+  const ConvTable* table;    // device copy of the conversion table
+  double* gcoef;             // [p_count][nbins][T]
+  double* grad_w;            // [n] cell order
+};
+hipError_t launch_adj_coef(const AdjArgs& a, hipStream_t st);
+hipError_t launch_unpermute(const double* gs, const int* perm, int64_t n, int accumulate,
+                            double* grad, hipStream_t st);
+// Device address of the uploaded conversion table of a basis.
+hipError_t conv_table_device(int basis, const ConvTable** out);
+
+size_t scan_tmp_bytes(int64_t count);
+hipError_t launch_scan(const int* in, int* out, int64_t count, void* tmp, size_t tmp_bytes,
+                       hipStream_t st);
+
+int sum_wm2(const RowLayout& lay);
+
+}  // namespace g3

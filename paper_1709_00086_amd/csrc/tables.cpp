@@ -1,0 +1,209 @@
+// Monomial-sum -> a_lm conversion coefficients (host code).
+//
+// On the unit sphere every Y_lm is a polynomial in the direction cosines, so
+// a_lm = sum_j w_j conj(Y_lm(u_j)) is a fixed linear combination of monomial
+// sums (paper, Sec. 3.1: the coefficients are weighted sums of the power
+// combinations of eq. 1).  With the Condon-Shortley phase,
+//
+//   conj(Y_lm(u)) = N_lm (-1)^m (u_x - i u_y)^m  d^m P_l / dz^m (u_z),
+//   N_lm = sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!),
+//   d^m P_l/dz^m (z) = 2^-l sum_k (-1)^k C(l,k) C(2l-2k,l) (l-2k)!/(l-2k-m)! z^{l-2k-m}
+//
+// (explicit form of P_l from Rodrigues' formula, differentiated m times).
+//
+// Spin basis: the sums S_{m,n} = sum w (u_x - i u_y)^m u_z^n give
+//   a_lm = N_lm (-1)^m sum_k c_lmk S_{m, l-m-2k}   (real c_lmk).
+// Cartesian basis (the paper's monomials): every term above is made
+// homogeneous of degree l with (u_x^2 + u_y^2 + u_z^2)^k = 1 and expanded with
+// the binomial and trinomial theorems, so only degree-l monomials
+// u_x^K u_y^P u_z^Q (K + P + Q = l) appear.
+//
+// Integer parts are accumulated exactly in int64, then scaled in double.
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <tuple>
+#include <vector>
+
+#include "internal.h"
+
+namespace g3 {
+
+namespace {
+
+int64_t binom(int n, int k) {
+  if (k < 0 || k > n) return 0;
+  int64_t r = 1;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+
+int64_t falling(int n, int k) {  // n! / (n-k)!
+  int64_t r = 1;
+  for (int i = 0; i < k; ++i) r *= (n - i);
+  return r;
+}
+
+int64_t fact(int n) { return falling(n, n); }
+
+double norm_lm(int l, int m) {
+  double ratio = 1.0;  // (l-m)!/(l+m)!
+  for (int i = l - m + 1; i <= l + m; ++i) ratio /= double(i);
+  return std::sqrt((2.0 * l + 1.0) / (4.0 * M_PI) * ratio);
+}
+
+// 2^l * c_lmk (an integer), c_lmk as defined above.
+int64_t c_int(int l, int m, int k) {
+  int64_t v = binom(l, k) * binom(2 * l - 2 * k, l) * falling(l - 2 * k, m);
+  return (k & 1) ? -v : v;
+}
+
+}  // namespace
+
+// Canonical term index of the cartesian monomial u_x^k u_y^p u_z^q
+// (q outermost, then p, then k), matching the pair kernels.
+int cart_index(int k, int p, int q) {
+  int t = 0;
+  for (int qq = 0; qq < q; ++qq) {
+    const int n = kDeg - qq;
+    t += (n + 1) * (n + 2) / 2;
+  }
+  for (int pp = 0; pp < p; ++pp) t += kDeg - q - pp + 1;
+  return t + k;
+}
+
+// Canonical term index of Re/Im S_{m,n} in the spin basis.
+int spin_index(int m, int n, int part) {
+  if (m == 0) return n;
+  int base = kDeg + 1;
+  for (int mm = 1; mm < m; ++mm) base += 2 * (kDeg + 1 - mm);
+  return base + 2 * n + part;
+}
+
+void build_conv_table(int basis, ConvTable* t) {
+  std::memset(t, 0, sizeof(*t));
+  int o = 0, nnz = 0;
+  for (int m = 0; m <= kDeg; ++m) {
+    for (int part = 0; part < (m == 0 ? 1 : 2); ++part) {
+      for (int l = m; l <= kDeg; ++l) {
+        t->out_m[o] = short(m);
+        t->out_l[o] = short(l);
+        t->out_part[o] = short(part);
+        t->rowptr[o] = nnz;
+        const double scale = norm_lm(l, m) * ((m & 1) ? -1.0 : 1.0) / std::ldexp(1.0, l);
+        if (basis == G3PCF_BASIS_SPIN) {
+          for (int k = 0; 2 * k <= l - m; ++k) {
+            t->term[nnz] = short(spin_index(m, l - m - 2 * k, part));
+            t->coef[nnz] = scale * double(c_int(l, m, k));
+            ++nnz;
+          }
+        } else {
+          // exact integer coefficients of u_x^K u_y^P u_z^Q for this (l, m, part)
+          std::map<std::tuple<int, int, int>, int64_t> acc;
+          for (int k = 0; 2 * k <= l - m; ++k) {
+            const int64_t ck = c_int(l, m, k);
+            for (int a = 0; a <= m; ++a) {
+              // (-i)^a: a%4 = 0 -> +1 (real), 1 -> -i, 2 -> -1 (real), 3 -> +i
+              const int am = a & 3;
+              const bool is_real = (am == 0 || am == 2);
+              if ((part == 0) != is_real) continue;
+              const int sgn = (am == 0 || am == 3) ? 1 : -1;
+              const int64_t cma = binom(m, a);
+              for (int k1 = 0; k1 <= k; ++k1)
+                for (int k2 = 0; k1 + k2 <= k; ++k2) {
+                  const int k3 = k - k1 - k2;
+                  const int64_t multi = fact(k) / (fact(k1) * fact(k2) * fact(k3));
+                  const int K = m - a + 2 * k1, P = a + 2 * k2, Q = l - m - 2 * k + 2 * k3;
+                  acc[std::make_tuple(K, P, Q)] += sgn * ck * cma * multi;
+                }
+            }
+          }
+          for (auto& kv : acc) {
+            if (kv.second == 0) continue;
+            int K, P, Q;
+            std::tie(K, P, Q) = kv.first;
+            t->term[nnz] = short(cart_index(K, P, Q));
+            t->coef[nnz] = scale * double(kv.second);
+            ++nnz;
+          }
+        }
+        ++o;
+      }
+    }
+  }
+  t->rowptr[o] = nnz;
+  t->nout = o;
+  t->nnz = nnz;
+  // transpose: entries grouped by term
+  const int nterm = (basis == G3PCF_BASIS_SPIN) ? kTermsSpin : kTermsCart;
+  std::vector<int> cnt(nterm + 1, 0);
+  for (int e = 0; e < nnz; ++e) cnt[t->term[e] + 1]++;
+  for (int k = 0; k < nterm; ++k) cnt[k + 1] += cnt[k];
+  for (int k = 0; k <= nterm; ++k) t->trowptr[k] = cnt[k];
+  for (int k = nterm + 1; k <= kTermsCart; ++k) t->trowptr[k] = cnt[nterm];
+  std::vector<int> fillp(cnt.begin(), cnt.end() - 1);
+  for (int oo = 0; oo < o; ++oo)
+    for (int e = t->rowptr[oo]; e < t->rowptr[oo + 1]; ++e) {
+      const int at = fillp[t->term[e]]++;
+      t->tout[at] = short(oo);
+      t->tcoef[at] = t->coef[e];
+    }
+}
+
+}  // namespace g3
+
+// Host-side evaluation of the library's conversion for one unit vector and
+// unit weight: out[(l*(l+1)/2 + m)*2 + {0,1}] = conj(Y_lm(u)) via the monomial
+// sums of `basis`.  Declared in g3pcf.h as a diagnostic.
+extern "C" int g3pcf_conj_ylm_via_monomials(int basis, int lmax, double ux, double uy,
+                                            double uz, double* out) {
+  using namespace g3;
+  if ((basis != G3PCF_BASIS_CARTESIAN && basis != G3PCF_BASIS_SPIN) || lmax < 0 ||
+      lmax > kDeg || out == nullptr)
+    return G3PCF_EINVAL;
+  static thread_local ConvTable tab[2];
+  static thread_local bool built[2] = {false, false};
+  if (!built[basis]) {
+    build_conv_table(basis, &tab[basis]);
+    built[basis] = true;
+  }
+  const ConvTable& t = tab[basis];
+  std::vector<double> M(basis == G3PCF_BASIS_SPIN ? kTermsSpin : kTermsCart, 0.0);
+  if (basis == G3PCF_BASIS_SPIN) {
+    double cr = 1.0, ci = 0.0;  // (ux - i uy)^m
+    for (int m = 0; m <= kDeg; ++m) {
+      double zn = 1.0;
+      for (int n = 0; m + n <= kDeg; ++n) {
+        if (m == 0) {
+          M[spin_index(0, n, 0)] = zn;
+        } else {
+          M[spin_index(m, n, 0)] = cr * zn;
+          M[spin_index(m, n, 1)] = ci * zn;
+        }
+        zn *= uz;
+      }
+      const double nr = cr * ux + ci * uy, ni = ci * ux - cr * uy;
+      cr = nr;
+      ci = ni;
+    }
+  } else {
+    for (int q = 0; q <= kDeg; ++q)
+      for (int p = 0; p + q <= kDeg; ++p)
+        for (int k = 0; k + p + q <= kDeg; ++k)
+          M[cart_index(k, p, q)] = std::pow(ux, k) * std::pow(uy, p) * std::pow(uz, q);
+  }
+  for (int l = 0; l <= lmax; ++l)
+    for (int m = 0; m <= l; ++m) {
+      out[2 * (l * (l + 1) / 2 + m)] = 0.0;
+      out[2 * (l * (l + 1) / 2 + m) + 1] = 0.0;
+    }
+  for (int o = 0; o < t.nout; ++o) {
+    const int l = t.out_l[o], m = t.out_m[o], part = t.out_part[o];
+    if (l > lmax) continue;
+    double s = 0.0;
+    for (int e = t.rowptr[o]; e < t.rowptr[o + 1]; ++e) s += t.coef[e] * M[t.term[e]];
+    out[2 * (l * (l + 1) / 2 + m) + part] = s;
+  }
+  return G3PCF_OK;
+}

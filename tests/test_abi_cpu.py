@@ -1,0 +1,166 @@
+"""Host-side checks of libg3pcf.so that need no GPU.
+
+The library must load, export every function include/g3pcf.h declares, report
+sizes that match the paper's counts, validate arguments synchronously (before
+any HIP call) and carry a monomial-to-Y_lm table that reproduces SciPy's
+spherical harmonics.
+"""
+import ctypes
+import json
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1709_00086_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "g3pcf.h")
+GOLDEN = os.path.join(ROOT, "tests", "golden", "paper_numbers.json")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1709_00086_amd import build
+        build.build(verbose=False)
+    return _lib.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(g3pcf_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 7
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(_lib.EXPORTED) == names
+
+
+def test_sizes_match_the_paper(lib):
+    gold = json.load(open(GOLDEN))
+    assert _lib.num_terms(_lib.BASIS_CARTESIAN) == gold["monomials_lmax10"]["value"]
+    l = gold["lmax"]["value"]
+    assert (l + 1) * (l + 2) * (l + 3) // 6 == _lib.num_terms(_lib.BASIS_CARTESIAN)
+    assert _lib.num_terms(_lib.BASIS_SPIN) == (l + 1) ** 2
+    assert _lib.num_terms(7) == -1
+    assert _lib.zeta_len(10, 10) == 11 ** 3 * 100 * 2
+    assert _lib.zeta_len(3, 4) == 4 ** 3 * 16 * 2
+    # the paper's flop-per-byte bound and working set for its bucket of k = 128 pairs
+    T = _lib.num_terms(_lib.BASIS_CARTESIAN)
+    k = 128
+    assert abs(T * 2 * k / ((3 * k + T * 2) * 8) - gold["flop_per_byte_k128"]["value"]) < 0.05
+    assert abs(T * 2 / (3 * 8) - gold["flop_per_byte_large_k"]["value"]) < 0.05
+    assert 128 * 8 * 3 + T * 8 * 8 == gold["working_set_bytes"]["value"]
+
+
+@pytest.mark.parametrize("basis", [_lib.BASIS_CARTESIAN, _lib.BASIS_SPIN])
+def test_conversion_table_reproduces_scipy_ylm(lib, basis):
+    from scipy.special import sph_harm_y
+    rng = np.random.default_rng(3)
+    U = rng.standard_normal((300, 3))
+    U /= np.linalg.norm(U, axis=1, keepdims=True)
+    U = np.concatenate([U, [[0, 0, 1.0], [0, 0, -1.0], [1.0, 0, 0], [0.0, 0.6, 0.8]]])
+    lmax = 10
+    for u in U:
+        got = np.array(_lib.conj_ylm_via_monomials(basis, lmax, u))
+        th = math.atan2(math.hypot(u[0], u[1]), u[2])
+        ph = math.atan2(u[1], u[0])
+        ref = np.array([np.conj(sph_harm_y(l, m, th, ph)) for l in range(lmax + 1)
+                        for m in range(l + 1)])
+        assert np.abs(got - ref).max() <= 1e-13
+
+
+def _problem(**kw):
+    p = _lib.Problem()
+    p.n = kw.get("n", 100)
+    p.pos = kw.get("pos", 0x1000)
+    p.pos_dtype = kw.get("pos_dtype", _lib.F64)
+    p.w = kw.get("w", 0x2000)
+    for k in range(3):
+        p.box[k] = kw.get("box", (100.0, 100.0, 100.0))[k]
+        p.box_lo[k] = 0.0
+        p.observer[k] = kw.get("observer", (0.0, 0.0, 0.0))[k]
+    p.periodic = kw.get("periodic", 1)
+    p.rmax = kw.get("rmax", 20.0)
+    p.nbins = kw.get("nbins", 4)
+    p.lmax = kw.get("lmax", 4)
+    p.los = kw.get("los", _lib.LOS_Z)
+    p.pair_prec = kw.get("pair_prec", _lib.PREC_FP32)
+    p.zeta_prec = kw.get("zeta_prec", _lib.PREC_FP32)
+    p.basis = kw.get("basis", _lib.BASIS_CARTESIAN)
+    p.primary_mask = None
+    p.accumulate = kw.get("accumulate", 0)
+    p.pairs_out = None
+    return p
+
+
+@pytest.mark.parametrize("kw", [
+    dict(rmax=51.0),                  # periodic needs rmax <= L/2
+    dict(rmax=-1.0),
+    dict(rmax=float("nan")),
+    dict(lmax=11),
+    dict(lmax=-1),
+    dict(nbins=0),
+    dict(nbins=33),
+    dict(n=-5),
+    dict(pos=None),
+    dict(pos_dtype=7),
+    dict(box=(100.0, 0.0, 100.0)),
+    dict(los=5),
+    dict(los=_lib.LOS_OBSERVER, observer=(float("inf"), 0.0, 0.0)),
+    dict(pair_prec=_lib.PREC_BF16X3),
+    dict(zeta_prec=9),
+    dict(basis=3),
+    dict(accumulate=2),
+])
+def test_invalid_arguments_are_rejected_before_any_device_work(lib, kw):
+    p = _problem(**kw)
+    out = ctypes.c_size_t(0)
+    rc = lib.g3pcf_workspace_bytes(ctypes.byref(p), 0, ctypes.byref(out))
+    assert rc == _lib.EINVAL
+    assert len(lib.g3pcf_last_error()) > 0
+    # the forward pass validates the same way and never reaches the device
+    rc = lib.g3pcf_forward(ctypes.byref(p), ctypes.c_void_p(0x3000), None, 0, None)
+    assert rc == _lib.EINVAL
+
+
+def test_workspace_too_small_is_reported(lib):
+    p = _problem()
+    need = _lib.workspace_bytes(p, 0)
+    assert need > 0
+    rc = lib.g3pcf_forward(ctypes.byref(p), ctypes.c_void_p(0x3000), None, 0, None)
+    assert rc == _lib.EWORKSPACE
+    rc = lib.g3pcf_forward(ctypes.byref(p), ctypes.c_void_p(0x3000), ctypes.c_void_p(0x100000),
+                           need - 1, None)
+    assert rc == _lib.EWORKSPACE
+    assert b"workspace" in lib.g3pcf_last_error()
+    rc = lib.g3pcf_backward(ctypes.byref(p), ctypes.c_void_p(0x3000), ctypes.c_void_p(0x4000),
+                            None, 0, None)
+    assert rc == _lib.EWORKSPACE
+
+
+def test_workspace_depends_only_on_sizes(lib):
+    a = _lib.workspace_bytes(_problem(pos=0x1000), 0)
+    b = _lib.workspace_bytes(_problem(pos=0x9000), 0)
+    assert a == b
+    assert _lib.workspace_bytes(_problem(), 1) > 0
+    big = _lib.workspace_bytes(_problem(n=1 << 20, box=(1000.0,) * 3, rmax=200.0, nbins=10,
+                                        lmax=10), 0)
+    assert big < 8 * (1 << 30)
+
+
+def test_null_pointers_rejected(lib):
+    out = ctypes.c_size_t(0)
+    assert lib.g3pcf_workspace_bytes(None, 0, ctypes.byref(out)) == _lib.EINVAL
+    p = _problem()
+    assert lib.g3pcf_workspace_bytes(ctypes.byref(p), 0, None) == _lib.EINVAL
+    assert lib.g3pcf_workspace_bytes(ctypes.byref(p), 2, ctypes.byref(out)) == _lib.EINVAL
+    assert lib.g3pcf_forward(ctypes.byref(p), None, None, 0, None) == _lib.EINVAL
+    assert lib.g3pcf_backward(ctypes.byref(p), None, None, None, 0, None) == _lib.EINVAL
