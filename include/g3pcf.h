@@ -76,6 +76,18 @@ typedef enum {
                                 sums per shell; the same zeta with fewer FMAs    */
 } g3pcf_basis;
 
+/* Stages reported by a trace (see g3pcf_trace_create). */
+typedef enum {
+  G3PCF_STAGE_CELLS = 0,        /* wrap, cell assignment, counting sort, primaries */
+  G3PCF_STAGE_PAIRS = 1,        /* pair kernel: search, rotate, bin, accumulate, convert */
+  G3PCF_STAGE_ZETA = 2,         /* Gram products on MFMA + FP64 accumulation       */
+  G3PCF_STAGE_ADJ_COEF = 3,     /* adjoint: U, V, H and monomial coefficients      */
+  G3PCF_STAGE_PAIR_ADJOINT = 4  /* adjoint pair kernel: polynomial + scatter        */
+} g3pcf_stage;
+
+/* Opaque record of per-stage GPU time.  Created on the current device. */
+typedef struct g3pcf_trace g3pcf_trace;
+
 typedef struct {
   int64_t n;               /* number of galaxies, 0 <= n < 2^31                  */
   const void* pos;         /* [n][3] row-major positions, dtype pos_dtype         */
@@ -102,7 +114,28 @@ typedef struct {
   int64_t* pairs_out;      /* HOST pointer or NULL.  If set, the call waits for
                               the stream and stores the number of accepted
                               ordered (primary, secondary) pairs                 */
+  g3pcf_trace* trace;      /* HOST handle or NULL.  If set, a pair of HIP events is
+                              recorded on `stream` around every stage launch
+                              (no synchronisation); read with g3pcf_trace_read */
 } g3pcf_problem;
+
+/* Trace with room for `capacity` stage records (2 * capacity HIP events on the
+ * current device).  Returns NULL if capacity < 1 or event creation fails. */
+g3pcf_trace* g3pcf_trace_create(int capacity);
+
+/* Forget all records (events are reused).  The caller must make sure no
+ * recorded event is still pending on a stream. */
+void g3pcf_trace_reset(g3pcf_trace* trace);
+
+/* After the traced streams are synchronised: copy up to `max` records as
+ * (stage, milliseconds) into HOST arrays and return the number copied, or a
+ * negative status (G3PCF_EINVAL for NULL arguments, G3PCF_EHIP if an event is
+ * not complete).  Records beyond the capacity were dropped; *dropped (HOST,
+ * may be NULL) receives their number. */
+int g3pcf_trace_read(g3pcf_trace* trace, int* stage, float* ms, int max, int* dropped);
+
+/* Destroy the trace and its events. */
+void g3pcf_trace_destroy(g3pcf_trace* trace);
 
 /* Number of doubles in zeta for (lmax, nbins): (lmax+1)^3 * nbins^2 * 2.
  * Layout [m][l][l'][b1][b2][re, im]; entries with l < m or l' < m are zero.

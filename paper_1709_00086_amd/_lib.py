@@ -18,7 +18,10 @@ F32, F64 = 0, 1
 BASIS_CARTESIAN, BASIS_SPIN = 0, 1
 
 EXPORTED = ["g3pcf_zeta_len", "g3pcf_num_terms", "g3pcf_workspace_bytes", "g3pcf_forward",
-            "g3pcf_backward", "g3pcf_last_error", "g3pcf_conj_ylm_via_monomials"]
+            "g3pcf_backward", "g3pcf_last_error", "g3pcf_conj_ylm_via_monomials",
+            "g3pcf_trace_create", "g3pcf_trace_reset", "g3pcf_trace_read",
+            "g3pcf_trace_destroy"]
+STAGES = {0: "cells", 1: "pairs", 2: "zeta", 3: "adj_coef", 4: "pair_adjoint"}
 
 
 class Problem(ctypes.Structure):
@@ -41,6 +44,7 @@ class Problem(ctypes.Structure):
         ("primary_mask", ctypes.c_void_p),
         ("accumulate", ctypes.c_int),
         ("pairs_out", ctypes.POINTER(ctypes.c_int64)),
+        ("trace", ctypes.c_void_p),
     ]
 
 
@@ -82,6 +86,16 @@ def load():
                                                  ctypes.c_double, ctypes.c_double,
                                                  ctypes.POINTER(ctypes.c_double)]
     lib.g3pcf_conj_ylm_via_monomials.restype = ctypes.c_int
+    lib.g3pcf_trace_create.argtypes = [ctypes.c_int]
+    lib.g3pcf_trace_create.restype = ctypes.c_void_p
+    lib.g3pcf_trace_reset.argtypes = [ctypes.c_void_p]
+    lib.g3pcf_trace_reset.restype = None
+    lib.g3pcf_trace_read.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int),
+                                     ctypes.POINTER(ctypes.c_float), ctypes.c_int,
+                                     ctypes.POINTER(ctypes.c_int)]
+    lib.g3pcf_trace_read.restype = ctypes.c_int
+    lib.g3pcf_trace_destroy.argtypes = [ctypes.c_void_p]
+    lib.g3pcf_trace_destroy.restype = None
     _lib = lib
     return lib
 
@@ -124,3 +138,36 @@ def conj_ylm_via_monomials(basis: int, lmax: int, u) -> list:
     check(load().g3pcf_conj_ylm_via_monomials(int(basis), int(lmax), float(u[0]), float(u[1]),
                                               float(u[2]), out))
     return [complex(out[2 * k], out[2 * k + 1]) for k in range(n // 2)]
+
+
+class Trace:
+    """Per-stage HIP-event timing recorded by the library on its stream."""
+
+    def __init__(self, capacity: int = 8192):
+        self.capacity = capacity
+        self.handle = load().g3pcf_trace_create(int(capacity))
+        if not self.handle:
+            raise G3pcfError(EHIP, load().g3pcf_last_error().decode(errors="replace"))
+
+    def reset(self):
+        load().g3pcf_trace_reset(self.handle)
+
+    def read(self):
+        """[(stage_name, ms), ...] -- call after synchronising the stream."""
+        st = (ctypes.c_int * self.capacity)()
+        ms = (ctypes.c_float * self.capacity)()
+        dropped = ctypes.c_int(0)
+        n = load().g3pcf_trace_read(self.handle, st, ms, self.capacity, ctypes.byref(dropped))
+        if n < 0:
+            check(n)
+        if dropped.value:
+            raise RuntimeError(f"trace dropped {dropped.value} records; raise its capacity")
+        return [(STAGES.get(st[k], str(st[k])), float(ms[k])) for k in range(n)]
+
+    def __del__(self):
+        try:
+            if self.handle:
+                load().g3pcf_trace_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass

@@ -56,7 +56,7 @@ def _require_cuda(t: torch.Tensor, name: str):
 
 def make_problem(pos: torch.Tensor, w: torch.Tensor, cfg: Config,
                  primary_mask: Optional[torch.Tensor] = None, accumulate: bool = False,
-                 pairs_out=None) -> _lib.Problem:
+                 pairs_out=None, trace: Optional["_lib.Trace"] = None) -> _lib.Problem:
     _require_cuda(pos, "pos")
     _require_cuda(w, "w")
     if pos.dim() != 2 or pos.shape[1] != 3:
@@ -93,6 +93,7 @@ def make_problem(pos: torch.Tensor, w: torch.Tensor, cfg: Config,
         p.primary_mask = None
     p.accumulate = 1 if accumulate else 0
     p.pairs_out = pairs_out
+    p.trace = trace.handle if trace is not None else None
     return p
 
 
@@ -115,12 +116,12 @@ _default_ws = Workspace()
 def zeta(pos: torch.Tensor, w: torch.Tensor, cfg: Config,
          primary_mask: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
          accumulate: bool = False, workspace: Optional[Workspace] = None,
-         return_pairs: bool = False):
+         return_pairs: bool = False, trace: Optional["_lib.Trace"] = None):
     """zeta^m_{l l'}(b1, b2) as a float64 device tensor [m][l][l'][b1][b2][re, im]."""
     import ctypes
     pairs = ctypes.c_int64(0)
     p = make_problem(pos, w, cfg, primary_mask, accumulate,
-                     ctypes.pointer(pairs) if return_pairs else None)
+                     ctypes.pointer(pairs) if return_pairs else None, trace)
     shape = zeta_shape(cfg.lmax, cfg.nbins)
     if out is None:
         out = torch.empty(shape, dtype=torch.float64, device=pos.device)
@@ -136,9 +137,10 @@ def zeta(pos: torch.Tensor, w: torch.Tensor, cfg: Config,
 
 def zeta_backward(pos: torch.Tensor, w: torch.Tensor, cfg: Config, grad_zeta: torch.Tensor,
                   primary_mask: Optional[torch.Tensor] = None,
-                  workspace: Optional[Workspace] = None) -> torch.Tensor:
+                  workspace: Optional[Workspace] = None,
+                  trace: Optional["_lib.Trace"] = None) -> torch.Tensor:
     """d(sum grad_zeta * zeta)/dw as a float64 device tensor (n,)."""
-    p = make_problem(pos, w, cfg, primary_mask)
+    p = make_problem(pos, w, cfg, primary_mask, trace=trace)
     shape = zeta_shape(cfg.lmax, cfg.nbins)
     gz = grad_zeta.to(torch.float64).contiguous()
     if gz.shape != shape:

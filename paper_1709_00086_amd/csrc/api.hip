@@ -10,10 +10,40 @@
 #include <string>
 #include <utility>
 
+#include <vector>
+
 #include "internal.h"
+
+struct g3pcf_trace {
+  int capacity = 0;
+  int count = 0;
+  int dropped = 0;
+  std::vector<hipEvent_t> ev;  // start, stop per record
+  std::vector<int> stage;
+};
 
 namespace g3 {
 namespace {
+
+// Records a start event now and a stop event when the scope ends.
+struct StageScope {
+  g3pcf_trace* t;
+  hipStream_t st;
+  int slot = -1;
+  StageScope(g3pcf_trace* tr, int stg, hipStream_t s) : t(tr), st(s) {
+    if (!t) return;
+    if (t->count < t->capacity) {
+      slot = t->count++;
+      t->stage[slot] = stg;
+      (void)hipEventRecord(t->ev[2 * slot], st);
+    } else {
+      ++t->dropped;
+    }
+  }
+  ~StageScope() {
+    if (slot >= 0) (void)hipEventRecord(t->ev[2 * slot + 1], st);
+  }
+};
 
 thread_local std::string t_err;
 
@@ -233,6 +263,53 @@ int g3pcf_num_terms(int basis) {
 
 const char* g3pcf_last_error(void) { return t_err.c_str(); }
 
+g3pcf_trace* g3pcf_trace_create(int capacity) {
+  if (capacity < 1) {
+    fail(G3PCF_EINVAL, "trace capacity must be >= 1");
+    return nullptr;
+  }
+  g3pcf_trace* t = new g3pcf_trace;
+  t->capacity = capacity;
+  t->ev.assign(2 * size_t(capacity), nullptr);
+  t->stage.assign(size_t(capacity), -1);
+  for (auto& e : t->ev) {
+    if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+      g3pcf_trace_destroy(t);
+      fail(G3PCF_EHIP, "hipEventCreate failed");
+      return nullptr;
+    }
+  }
+  return t;
+}
+
+void g3pcf_trace_reset(g3pcf_trace* t) {
+  if (!t) return;
+  t->count = 0;
+  t->dropped = 0;
+}
+
+int g3pcf_trace_read(g3pcf_trace* t, int* stage, float* ms, int max, int* dropped) {
+  if (!t || !stage || !ms || max < 0) return fail(G3PCF_EINVAL, "NULL trace or output");
+  const int n = std::min(max, t->count);
+  for (int k = 0; k < n; ++k) {
+    float v = 0.f;
+    hipError_t e = hipEventElapsedTime(&v, t->ev[2 * k], t->ev[2 * k + 1]);
+    if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+    stage[k] = t->stage[k];
+    ms[k] = v;
+  }
+  if (dropped) *dropped = t->dropped;
+  return n;
+}
+
+void g3pcf_trace_destroy(g3pcf_trace* t) {
+  if (!t) return;
+  for (auto& e : t->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete t;
+}
+
 int g3pcf_workspace_bytes(const g3pcf_problem* prob, int backward, size_t* bytes) {
   int rc = validate(prob);
   if (rc) return rc;
@@ -263,15 +340,22 @@ int g3pcf_forward(const g3pcf_problem* prob, double* zeta, void* ws, size_t ws_b
     if (p.pairs_out) *p.pairs_out = 0;
     return G3PCF_OK;
   }
-  if ((rc = stage_catalogue(p, w, ws, st))) return rc;
+  {
+    StageScope sc(p.trace, G3PCF_STAGE_CELLS, st);
+    if ((rc = stage_catalogue(p, w, ws, st))) return rc;
+  }
   PairArgs a = pair_args(p, w, ws);
   const int fp64 = (p.pair_prec == G3PCF_PREC_FP64);
   Counters* c = at<Counters>(ws, w.counters);
   for (int64_t b0 = 0; b0 < p.n; b0 += w.PB) {
     a.p_begin = b0;
     a.p_count = std::min<int64_t>(w.PB, p.n - b0);
-    if ((e = launch_pair_forward(a, fp64, p.basis, st)) != hipSuccess)
-      return hip_fail(e, "pair kernel");
+    {
+      StageScope sc(p.trace, G3PCF_STAGE_PAIRS, st);
+      if ((e = launch_pair_forward(a, fp64, p.basis, st)) != hipSuccess)
+        return hip_fail(e, "pair kernel");
+    }
+    StageScope scz(p.trace, G3PCF_STAGE_ZETA, st);
     for (int64_t s0 = 0; s0 < a.p_count; s0 += kZetaBlock) {
       ZetaArgs z{};
       z.A = a.A;
@@ -312,7 +396,10 @@ int g3pcf_backward(const g3pcf_problem* prob, const double* grad_zeta, double* g
     return G3PCF_OK;
   }
   hipError_t e;
-  if ((rc = stage_catalogue(p, w, ws, st))) return rc;
+  {
+    StageScope sc(p.trace, G3PCF_STAGE_CELLS, st);
+    if ((rc = stage_catalogue(p, w, ws, st))) return rc;
+  }
   double* gsort = at<double>(ws, w.gsort);
   if ((e = launch_fill_double(gsort, p.n, 0.0, st)) != hipSuccess)
     return hip_fail(e, "gradient clear");
@@ -327,8 +414,11 @@ int g3pcf_backward(const g3pcf_problem* prob, const double* grad_zeta, double* g
     a.p_begin = b0;
     a.p_count = std::min<int64_t>(w.PB, p.n - b0);
     a.pairs = &c->pairs;
-    if ((e = launch_pair_forward(a, fp64, p.basis, st)) != hipSuccess)
-      return hip_fail(e, "pair kernel (recompute)");
+    {
+      StageScope sc(p.trace, G3PCF_STAGE_PAIRS, st);
+      if ((e = launch_pair_forward(a, fp64, p.basis, st)) != hipSuccess)
+        return hip_fail(e, "pair kernel (recompute)");
+    }
     AdjArgs j{};
     j.A = a.A;
     j.gz = grad_zeta;
@@ -343,10 +433,16 @@ int g3pcf_backward(const g3pcf_problem* prob, const double* grad_zeta, double* g
     j.table = tab;
     j.gcoef = at<double>(ws, w.gcoef);
     j.grad_w = gsort;
-    if ((e = launch_adj_coef(j, st)) != hipSuccess) return hip_fail(e, "adjoint coefficients");
+    {
+      StageScope sc(p.trace, G3PCF_STAGE_ADJ_COEF, st);
+      if ((e = launch_adj_coef(j, st)) != hipSuccess) return hip_fail(e, "adjoint coefficients");
+    }
     a.pairs = &c->pairs_adj;
-    if ((e = launch_pair_adjoint(a, fp64, p.basis, st)) != hipSuccess)
-      return hip_fail(e, "pair adjoint kernel");
+    {
+      StageScope sc(p.trace, G3PCF_STAGE_PAIR_ADJOINT, st);
+      if ((e = launch_pair_adjoint(a, fp64, p.basis, st)) != hipSuccess)
+        return hip_fail(e, "pair adjoint kernel");
+    }
   }
   if ((e = launch_unpermute(gsort, a.perm, p.n, p.accumulate, grad_w, st)) != hipSuccess)
     return hip_fail(e, "gradient permute");

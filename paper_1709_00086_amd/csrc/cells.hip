@@ -260,6 +260,15 @@ Grid make_grid(const g3pcf_problem& p) {
   while (int64_t(g.nc[0]) * g.nc[1] * g.nc[2] > cap) {
     for (int a = 0; a < 3; ++a) g.nc[a] = std::max(1, (g.nc[a] * 4) / 5);
   }
+  // A search window must span at most kMaxRows (cy, cz) rows of cells.
+  auto window = [&](int a) {
+    const double s = g.L[a] / g.nc[a];
+    const int w = int(std::floor(2.0 * g.rsearch / s)) + 2;
+    return std::min(w, g.nc[a]);
+  };
+  while (window(1) * window(2) > kMaxRows) {
+    for (int a = 1; a < 3; ++a) g.nc[a] = std::max(1, std::min(g.nc[a] - 1, (g.nc[a] * 9) / 10));
+  }
   for (int a = 0; a < 3; ++a) {
     g.s[a] = g.L[a] / g.nc[a];
     g.inv_s[a] = double(g.nc[a]) / g.L[a];

@@ -30,6 +30,10 @@ constexpr int kPairWaves = 4096;
 constexpr int kPairBlockMax = 131072;
 // Per-wave scratch (neighbour indices) upper bound.
 constexpr int kScratchMax = 1 << 16;
+// Candidate runs per primary held in LDS: at most two per (cy, cz) row of
+// cells, and the grid is chosen so that a search window spans <= 128 rows.
+constexpr int kMaxSegments = 256;
+constexpr int kMaxRows = kMaxSegments / 2;
 
 // Sparse monomial -> a_lm conversion table, one row per real output of a
 // shell.  Output o = (m, part, l) with part 0 = Re, 1 = Im (m >= 1 only).

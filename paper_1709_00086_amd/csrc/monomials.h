@@ -1,0 +1,424 @@
+// Device helpers of the pair kernels: wave-uniform broadcasts, DPP wave sums
+// and the two monomial bases with their register-resident accumulators.
+//
+// Included by pairs.hip only (it opens an anonymous namespace).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+#include <utility>
+
+#include "internal.h"
+
+namespace g3 {
+namespace {
+
+// ---------------------------------------------------------------- utilities
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+template <typename Real>
+struct V4;
+template <>
+struct V4<float> {
+  using T = float4;
+};
+template <>
+struct V4<double> {
+  using T = double4;
+};
+
+__device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ double uniform_double(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane(int(b & 0xffffffffll));
+  const int hi = __builtin_amdgcn_readfirstlane(int(b >> 32));
+  return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                              (static_cast<unsigned int>(lo)));
+}
+
+// DPP move with compile-time controls (old value 0 where the row is masked).
+// With bound_ctrl set and full masks the compiler folds the move into the add.
+template <int CTRL, int ROW, int BANK>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROW, BANK, true);
+}
+
+// Sum over the 64 lanes; the total is valid in lanes 48..63.
+// quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_ror 4, row_ror 8 give every
+// lane its row sum; row_bcast 15 and row_bcast 31 then fold rows 0-2 into 3.
+__device__ __forceinline__ float wave_sum(float v) {
+  v += __int_as_float(dpp_i<0xB1, 0xF, 0xF>(__float_as_int(v)));
+  v += __int_as_float(dpp_i<0x4E, 0xF, 0xF>(__float_as_int(v)));
+  v += __int_as_float(dpp_i<0x124, 0xF, 0xF>(__float_as_int(v)));
+  v += __int_as_float(dpp_i<0x128, 0xF, 0xF>(__float_as_int(v)));
+  v += __int_as_float(dpp_i<0x142, 0xA, 0xF>(__float_as_int(v)));
+  v += __int_as_float(dpp_i<0x143, 0xC, 0xF>(__float_as_int(v)));
+  return v;
+}
+
+template <int CTRL, int ROW, int BANK>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp_i<CTRL, ROW, BANK>(int(b & 0xffffffffll));
+  const int hi = dpp_i<CTRL, ROW, BANK>(int(b >> 32));
+  return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                              (static_cast<unsigned int>(lo)));
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_d<0xB1, 0xF, 0xF>(v);
+  v += dpp_d<0x4E, 0xF, 0xF>(v);
+  v += dpp_d<0x124, 0xF, 0xF>(v);
+  v += dpp_d<0x128, 0xF, 0xF>(v);
+  v += dpp_d<0x142, 0xA, 0xF>(v);
+  v += dpp_d<0x143, 0xC, 0xF>(v);
+  return v;
+}
+
+// Sum over the 16 lanes of each row (every lane gets its row's sum).
+__device__ __forceinline__ float row_sum(float v) {
+  v += __int_as_float(dpp_i<0xB1, 0xF, 0xF>(__float_as_int(v)));
+  v += __int_as_float(dpp_i<0x4E, 0xF, 0xF>(__float_as_int(v)));
+  v += __int_as_float(dpp_i<0x124, 0xF, 0xF>(__float_as_int(v)));
+  v += __int_as_float(dpp_i<0x128, 0xF, 0xF>(__float_as_int(v)));
+  return v;
+}
+__device__ __forceinline__ double row_sum(double v) {
+  v += dpp_d<0xB1, 0xF, 0xF>(v);
+  v += dpp_d<0x4E, 0xF, 0xF>(v);
+  v += dpp_d<0x124, 0xF, 0xF>(v);
+  v += dpp_d<0x128, 0xF, 0xF>(v);
+  return v;
+}
+
+// Given row sums of four values a, e, b, f (rows 0..3 of each), return a
+// value whose row 0 holds the total of a, row 1 of e, row 2 of b, row 3 of f:
+// permlane32_swap exchanges the upper half of its first operand with the
+// lower half of its second, permlane16_swap the odd rows of its first with the
+// even rows of its second.
+__device__ __forceinline__ unsigned pl32(unsigned& x, unsigned y) {
+  const auto r = __builtin_amdgcn_permlane32_swap(x, y, false, false);
+  x = r[0];
+  return r[1];
+}
+__device__ __forceinline__ unsigned pl16(unsigned& x, unsigned y) {
+  const auto r = __builtin_amdgcn_permlane16_swap(x, y, false, false);
+  x = r[0];
+  return r[1];
+}
+__device__ __forceinline__ float fold4(float a, float e, float b, float f) {
+  unsigned ua = __float_as_uint(a), ue = __float_as_uint(e);
+  const unsigned ub = pl32(ua, __float_as_uint(b));
+  const unsigned uf = pl32(ue, __float_as_uint(f));
+  const float c = __uint_as_float(ua) + __uint_as_float(ub);
+  const float d = __uint_as_float(ue) + __uint_as_float(uf);
+  unsigned uc = __float_as_uint(c);
+  const unsigned ud = pl16(uc, __float_as_uint(d));
+  return __uint_as_float(uc) + __uint_as_float(ud);
+}
+__device__ __forceinline__ double swap32_d(double& x, double y) {
+  const long long bx = __double_as_longlong(x), by = __double_as_longlong(y);
+  unsigned xl = unsigned(bx), xh = unsigned(bx >> 32);
+  const unsigned yl = pl32(xl, unsigned(by)), yh = pl32(xh, unsigned(by >> 32));
+  x = __longlong_as_double((static_cast<long long>(xh) << 32) | xl);
+  return __longlong_as_double((static_cast<long long>(yh) << 32) | yl);
+}
+__device__ __forceinline__ double swap16_d(double& x, double y) {
+  const long long bx = __double_as_longlong(x), by = __double_as_longlong(y);
+  unsigned xl = unsigned(bx), xh = unsigned(bx >> 32);
+  const unsigned yl = pl16(xl, unsigned(by)), yh = pl16(xh, unsigned(by >> 32));
+  x = __longlong_as_double((static_cast<long long>(xh) << 32) | xl);
+  return __longlong_as_double((static_cast<long long>(yh) << 32) | yl);
+}
+__device__ __forceinline__ double fold4(double a, double e, double b, double f) {
+  const double b2 = swap32_d(a, b);
+  const double f2 = swap32_d(e, f);
+  double c = a + b2;
+  const double d = e + f2;
+  const double d2 = swap16_d(c, d);
+  return c + d2;
+}
+
+__device__ __forceinline__ float fma_r(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_r(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// ---------------------------------------------------------------- monomial bases
+// Canonical cartesian index (q outermost, then p, then k); must match tables.cpp.
+__host__ __device__ constexpr int cart_index_c(int k, int p, int q) {
+  int t = 0;
+  for (int qq = 0; qq < q; ++qq) t += (kDeg - qq + 1) * (kDeg - qq + 2) / 2;
+  for (int pp = 0; pp < p; ++pp) t += kDeg - q - pp + 1;
+  return t + k;
+}
+__host__ __device__ constexpr int spin_index_c(int m, int n, int part) {
+  int base = (m == 0) ? 0 : kDeg + 1;
+  for (int mm = 1; mm < m; ++mm) base += 2 * (kDeg + 1 - mm);
+  return (m == 0) ? n : base + 2 * n + part;
+}
+
+__host__ __device__ constexpr int cart_count(unsigned qmask) {
+  int c = 0;
+  for (int q = 0; q <= kDeg; ++q)
+    if ((qmask >> q) & 1u) c += (kDeg - q + 1) * (kDeg - q + 2) / 2;
+  return c;
+}
+// local index of (k, p, q) inside a chunk holding the q's of qmask
+__host__ __device__ constexpr int cart_local(unsigned qmask, int k, int p, int q) {
+  int t = 0;
+  for (int qq = 0; qq < q; ++qq)
+    if ((qmask >> qq) & 1u) t += (kDeg - qq + 1) * (kDeg - qq + 2) / 2;
+  for (int pp = 0; pp < p; ++pp) t += kDeg - q - pp + 1;
+  return t + k;
+}
+
+// Global term index of the i-th accumulator of a cartesian chunk.
+__host__ __device__ constexpr int cart_term_of(unsigned qmask, int i) {
+  int t = 0;
+  for (int q = 0; q <= kDeg; ++q) {
+    if (!((qmask >> q) & 1u)) continue;
+    for (int p = 0; p + q <= kDeg; ++p)
+      for (int k = 0; k + p + q <= kDeg; ++k) {
+        if (t == i) return cart_index_c(k, p, q);
+        ++t;
+      }
+  }
+  return -1;
+}
+
+// Cartesian chunk: the monomials u_x^k u_y^p u_z^q whose z power q is in QMASK.
+// Per pair: P = w u_y^p u_z^q by running products, then acc += u_x^k * P
+// (one FMA per monomial).
+template <typename Real, unsigned QMASK>
+struct CartChunk {
+  static constexpr int NT = cart_count(QMASK);
+  Real acc[NT];
+  static __host__ __device__ constexpr int term_of(int i) { return cart_term_of(QMASK, i); }
+
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int i = 0; i < NT; ++i) acc[i] = Real(0);
+  }
+
+  __device__ __forceinline__ void add(Real x, Real y, Real z, Real w) {
+    Real xp[kDeg + 1];
+    xp[0] = Real(1);
+#pragma unroll
+    for (int k = 1; k <= kDeg; ++k) xp[k] = xp[k - 1] * x;
+    Real wz = w;
+    static_for<kDeg + 1>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      if constexpr (q > 0) wz = wz * z;
+      if constexpr (((QMASK >> q) & 1u) != 0) {
+        Real P = wz;
+        static_for<kDeg + 1 - q>([&](auto pc) {
+          constexpr int p = decltype(pc)::value;
+          if constexpr (p > 0) P = P * y;
+          static_for<kDeg + 1 - q - p>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            constexpr int t = cart_local(QMASK, k, p, q);
+            if constexpr (k == 0)
+              acc[t] += P;
+            else
+              acc[t] = fma_r(xp[k], P, acc[t]);
+          });
+        });
+      }
+    });
+  }
+
+  // adjoint: sum over this chunk's monomials of g_t * monomial (Horner in x)
+  template <typename GetG>
+  static __device__ __forceinline__ Real poly(Real x, Real y, Real z, GetG&& g) {
+    Real total = Real(0);
+    Real zq = Real(1);
+    static_for<kDeg + 1>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      if constexpr (q > 0) zq = zq * z;
+      if constexpr (((QMASK >> q) & 1u) != 0) {
+        Real ysum = Real(0);  // sum_p y^p * (sum_k g x^k), Horner in y
+        static_for<kDeg + 1 - q>([&](auto pr) {
+          constexpr int p = kDeg - q - decltype(pr)::value;
+          Real hx = Real(0);
+          static_for<kDeg + 1 - q - p>([&](auto kr) {
+            constexpr int k = kDeg - q - p - decltype(kr)::value;
+            hx = fma_r(hx, x, g(cart_index_c(k, p, q)));
+          });
+          ysum = fma_r(ysum, y, hx);
+        });
+        total = fma_r(ysum, zq, total);
+      }
+    });
+    return total;
+  }
+
+  template <typename Store>
+  __device__ __forceinline__ void for_each_term(Store&& st) {
+    static_for<kDeg + 1>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      if constexpr (((QMASK >> q) & 1u) != 0) {
+        static_for<kDeg + 1 - q>([&](auto pc) {
+          constexpr int p = decltype(pc)::value;
+          static_for<kDeg + 1 - q - p>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            st(acc[cart_local(QMASK, k, p, q)], cart_index_c(k, p, q));
+          });
+        });
+      }
+    });
+  }
+};
+
+__host__ __device__ constexpr int spin_count(int m0, int m1) {
+  int c = 0;
+  for (int m = m0; m <= m1; ++m) c += (m == 0) ? (kDeg + 1) : 2 * (kDeg + 1 - m);
+  return c;
+}
+__host__ __device__ constexpr int spin_local(int m0, int m, int n, int part) {
+  int t = 0;
+  for (int mm = m0; mm < m; ++mm) t += (mm == 0) ? (kDeg + 1) : 2 * (kDeg + 1 - mm);
+  return (m == 0) ? t + n : t + 2 * n + part;
+}
+
+// Global term index of the i-th accumulator of a spin chunk (m0..m1).
+__host__ __device__ constexpr int spin_term_of(int m0, int m1, int i) {
+  int t = 0;
+  for (int m = m0; m <= m1; ++m)
+    for (int n = 0; m + n <= kDeg; ++n)
+      for (int part = 0; part < (m == 0 ? 1 : 2); ++part) {
+        if (t == i) return spin_index_c(m, n, part);
+        ++t;
+      }
+  return -1;
+}
+
+// Spin chunk: S_{m,n} = sum w (u_x - i u_y)^m u_z^n for M0 <= m <= M1.
+template <typename Real, int M0, int M1>
+struct SpinChunk {
+  static constexpr int NT = spin_count(M0, M1);
+  Real acc[NT];
+  static __host__ __device__ constexpr int term_of(int i) { return spin_term_of(M0, M1, i); }
+
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int i = 0; i < NT; ++i) acc[i] = Real(0);
+  }
+
+  __device__ __forceinline__ void add(Real x, Real y, Real z, Real w) {
+    constexpr int NMAX = kDeg - (M0 > 0 ? M0 : 0);
+    Real zn[kDeg + 1];
+    zn[0] = Real(1);
+#pragma unroll
+    for (int n = 1; n <= NMAX; ++n) zn[n] = zn[n - 1] * z;
+    if constexpr (M0 == 0) {
+      acc[spin_local(M0, 0, 0, 0)] += w;
+      static_for<kDeg>([&](auto nc) {
+        constexpr int n = decltype(nc)::value + 1;
+        acc[spin_local(M0, 0, n, 0)] = fma_r(w, zn[n], acc[spin_local(M0, 0, n, 0)]);
+      });
+    }
+    if constexpr (M1 >= 1) {
+      Real cr = w * x, ci = -(w * y);  // w (x - i y)
+      static_for<M1>([&](auto mc) {
+        constexpr int m = decltype(mc)::value + 1;
+        if constexpr (m > 1) {
+          const Real nr = fma_r(cr, x, ci * y);
+          const Real ni = fma_r(ci, x, -(cr * y));
+          cr = nr;
+          ci = ni;
+        }
+        if constexpr (m >= M0) {
+          acc[spin_local(M0, m, 0, 0)] += cr;
+          acc[spin_local(M0, m, 0, 1)] += ci;
+          static_for<kDeg - m>([&](auto nc) {
+            constexpr int n = decltype(nc)::value + 1;
+            acc[spin_local(M0, m, n, 0)] = fma_r(cr, zn[n], acc[spin_local(M0, m, n, 0)]);
+            acc[spin_local(M0, m, n, 1)] = fma_r(ci, zn[n], acc[spin_local(M0, m, n, 1)]);
+          });
+        }
+      });
+    }
+  }
+
+  // adjoint: sum over this chunk of g_t * Re/Im parts of (x - i y)^m z^n
+  template <typename GetG>
+  static __device__ __forceinline__ Real poly(Real x, Real y, Real z, GetG&& g) {
+    Real total = Real(0);
+    Real cr = Real(1), ci = Real(0);
+    static_for<M1 + 1>([&](auto mc) {
+      constexpr int m = decltype(mc)::value;
+      if constexpr (m > 0) {
+        const Real nr = fma_r(cr, x, ci * y);
+        const Real ni = fma_r(ci, x, -(cr * y));
+        cr = nr;
+        ci = ni;
+      }
+      if constexpr (m >= M0) {
+        // Horner in z over n for the Re and Im coefficient sets
+        Real hr = Real(0), hi = Real(0);
+        static_for<kDeg - m + 1>([&](auto nr_) {
+          constexpr int n = kDeg - m - decltype(nr_)::value;
+          hr = fma_r(hr, z, g(spin_index_c(m, n, 0)));
+          if constexpr (m > 0) hi = fma_r(hi, z, g(spin_index_c(m, n, 1)));
+        });
+        if constexpr (m == 0)
+          total += hr;
+        else
+          total = fma_r(cr, hr, fma_r(ci, hi, total));
+      }
+    });
+    return total;
+  }
+
+  template <typename Store>
+  __device__ __forceinline__ void for_each_term(Store&& st) {
+    static_for<M1 - M0 + 1>([&](auto mc) {
+      constexpr int m = decltype(mc)::value + M0;
+      static_for<kDeg - m + 1>([&](auto nc) {
+        constexpr int n = decltype(nc)::value;
+        st(acc[spin_local(M0, m, n, 0)], spin_index_c(m, n, 0));
+        if constexpr (m > 0) st(acc[spin_local(M0, m, n, 1)], spin_index_c(m, n, 1));
+      });
+    });
+  }
+};
+
+template <class... C>
+struct ChunkList {};
+
+// Chunking keeps each chunk's accumulators within the 256 architected VGPRs.
+template <typename Real, int BASIS>
+struct Chunks;
+template <>
+struct Chunks<float, G3PCF_BASIS_CARTESIAN> {
+  using type = ChunkList<CartChunk<float, 0x023u>, CartChunk<float, 0x7DCu>>;
+};
+template <>
+struct Chunks<double, G3PCF_BASIS_CARTESIAN> {
+  using type = ChunkList<CartChunk<double, 0x601u>, CartChunk<double, 0x182u>,
+                         CartChunk<double, 0x00Cu>, CartChunk<double, 0x070u>>;
+};
+template <>
+struct Chunks<float, G3PCF_BASIS_SPIN> {
+  using type = ChunkList<SpinChunk<float, 0, kDeg>>;
+};
+template <>
+struct Chunks<double, G3PCF_BASIS_SPIN> {
+  using type = ChunkList<SpinChunk<double, 0, 3>, SpinChunk<double, 4, kDeg>>;
+};
+
+template <class... C, typename F>
+__device__ __forceinline__ void for_each_chunk(ChunkList<C...>, F&& f) {
+  (f(static_cast<C*>(nullptr)), ...);
+}
+
+}  // namespace
+}  // namespace g3

@@ -5,25 +5,29 @@
 // One wavefront owns one primary at a time and pulls primaries from a shared
 // counter (dynamic scheduling over primaries, as the paper's OpenMP dynamic
 // schedule).  For its primary the wave
+//   0. builds a table of candidate runs in LDS: one lane per (cy, cz) row of
+//      cells, all cell-start lookups in flight at once;
 //   1. counts the accepted secondaries per radial shell (search pass 1);
 //   2. writes their indices into per-shell lists in its own scratch (search
 //      pass 2) -- the GPU form of the paper's per-shell pair buckets;
 //   3. for each shell streams its list with one pair per lane, accumulating
 //      every monomial sum in registers (vectorised over pairs, not over
-//      monomials, as in the paper's vectorisation section), then reduces the
-//      per-lane partials once per (primary, shell) with DPP;
+//      monomials, as in the paper's vectorisation section) with the gathers of
+//      the next pairs in flight, then reduces the per-lane partials once per
+//      (primary, shell) with DPP;
 //   4. converts the shell's monomial sums to a_lm in FP64 and writes them to
 //      the primary's row of A.
-// The candidate search walks (cy, cz) rows of the cell grid; each row's cells
-// within reach form one contiguous run of galaxies, read with coalesced loads.
+// The search passes load four candidates per lane before testing any, so a
+// wave keeps four loads in flight.
 #include <hip/hip_runtime.h>
 
-#include <cmath>
 #include <algorithm>
+#include <cmath>
 #include <type_traits>
 #include <utility>
 
 #include "internal.h"
+#include "monomials.h"
 
 namespace g3 {
 
@@ -50,333 +54,29 @@ hipError_t conv_table_device(int basis, const ConvTable** out) {
 
 namespace {
 
-// ---------------------------------------------------------------- utilities
-template <typename F, int... I>
-__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
-  (f(std::integral_constant<int, I>{}), ...);
-}
-template <int N, typename F>
-__device__ __forceinline__ void static_for(F&& f) {
-  static_for_impl(f, std::make_integer_sequence<int, N>{});
-}
-
-template <typename Real>
-struct V4;
-template <>
-struct V4<float> {
-  using T = float4;
-};
-template <>
-struct V4<double> {
-  using T = double4;
-};
-
-__device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
-
-__device__ __forceinline__ double uniform_double(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readfirstlane(int(b & 0xffffffffll));
-  const int hi = __builtin_amdgcn_readfirstlane(int(b >> 32));
-  return __longlong_as_double((static_cast<long long>(hi) << 32) |
-                              (static_cast<unsigned int>(lo)));
-}
-
-// DPP move with compile-time controls (old value 0 where the row is masked).
-template <int CTRL, int ROW, int BANK>
-__device__ __forceinline__ int dpp_i(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROW, BANK, false);
-}
-
-// Sum over the 64 lanes; the total is valid in lanes 48..63.
-// quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_ror 4, row_ror 8 give every
-// lane its row sum; row_bcast 15 and row_bcast 31 then fold rows 0-2 into 3.
-__device__ __forceinline__ float wave_sum(float v) {
-  v += __int_as_float(dpp_i<0xB1, 0xF, 0xF>(__float_as_int(v)));
-  v += __int_as_float(dpp_i<0x4E, 0xF, 0xF>(__float_as_int(v)));
-  v += __int_as_float(dpp_i<0x124, 0xF, 0xF>(__float_as_int(v)));
-  v += __int_as_float(dpp_i<0x128, 0xF, 0xF>(__float_as_int(v)));
-  v += __int_as_float(dpp_i<0x142, 0xA, 0xF>(__float_as_int(v)));
-  v += __int_as_float(dpp_i<0x143, 0xC, 0xF>(__float_as_int(v)));
-  return v;
-}
-
-template <int CTRL, int ROW, int BANK>
-__device__ __forceinline__ double dpp_d(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = dpp_i<CTRL, ROW, BANK>(int(b & 0xffffffffll));
-  const int hi = dpp_i<CTRL, ROW, BANK>(int(b >> 32));
-  return __longlong_as_double((static_cast<long long>(hi) << 32) |
-                              (static_cast<unsigned int>(lo)));
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-  v += dpp_d<0xB1, 0xF, 0xF>(v);
-  v += dpp_d<0x4E, 0xF, 0xF>(v);
-  v += dpp_d<0x124, 0xF, 0xF>(v);
-  v += dpp_d<0x128, 0xF, 0xF>(v);
-  v += dpp_d<0x142, 0xA, 0xF>(v);
-  v += dpp_d<0x143, 0xC, 0xF>(v);
-  return v;
-}
-
-__device__ __forceinline__ float fma_r(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double fma_r(double a, double b, double c) { return __builtin_fma(a, b, c); }
-
-// ---------------------------------------------------------------- monomial bases
-// Canonical cartesian index (q outermost, then p, then k); must match tables.cpp.
-__host__ __device__ constexpr int cart_index_c(int k, int p, int q) {
-  int t = 0;
-  for (int qq = 0; qq < q; ++qq) t += (kDeg - qq + 1) * (kDeg - qq + 2) / 2;
-  for (int pp = 0; pp < p; ++pp) t += kDeg - q - pp + 1;
-  return t + k;
-}
-__host__ __device__ constexpr int spin_index_c(int m, int n, int part) {
-  int base = (m == 0) ? 0 : kDeg + 1;
-  for (int mm = 1; mm < m; ++mm) base += 2 * (kDeg + 1 - mm);
-  return (m == 0) ? n : base + 2 * n + part;
-}
-
-__host__ __device__ constexpr int cart_count(unsigned qmask) {
-  int c = 0;
-  for (int q = 0; q <= kDeg; ++q)
-    if ((qmask >> q) & 1u) c += (kDeg - q + 1) * (kDeg - q + 2) / 2;
-  return c;
-}
-// local index of (k, p, q) inside a chunk holding the q's of qmask
-__host__ __device__ constexpr int cart_local(unsigned qmask, int k, int p, int q) {
-  int t = 0;
-  for (int qq = 0; qq < q; ++qq)
-    if ((qmask >> qq) & 1u) t += (kDeg - qq + 1) * (kDeg - qq + 2) / 2;
-  for (int pp = 0; pp < p; ++pp) t += kDeg - q - pp + 1;
-  return t + k;
-}
-
-// Cartesian chunk: the monomials u_x^k u_y^p u_z^q whose z power q is in QMASK.
-// Per pair: P = w u_y^p u_z^q by running products, then acc += u_x^k * P
-// (one FMA per monomial).
-template <typename Real, unsigned QMASK>
-struct CartChunk {
-  static constexpr int NT = cart_count(QMASK);
-  Real acc[NT];
-
-  __device__ __forceinline__ void zero() {
-#pragma unroll
-    for (int i = 0; i < NT; ++i) acc[i] = Real(0);
-  }
-
-  __device__ __forceinline__ void add(Real x, Real y, Real z, Real w) {
-    Real xp[kDeg + 1];
-    xp[0] = Real(1);
-#pragma unroll
-    for (int k = 1; k <= kDeg; ++k) xp[k] = xp[k - 1] * x;
-    Real wz = w;
-    static_for<kDeg + 1>([&](auto qc) {
-      constexpr int q = decltype(qc)::value;
-      if constexpr (q > 0) wz = wz * z;
-      if constexpr (((QMASK >> q) & 1u) != 0) {
-        Real P = wz;
-        static_for<kDeg + 1 - q>([&](auto pc) {
-          constexpr int p = decltype(pc)::value;
-          if constexpr (p > 0) P = P * y;
-          static_for<kDeg + 1 - q - p>([&](auto kc) {
-            constexpr int k = decltype(kc)::value;
-            constexpr int t = cart_local(QMASK, k, p, q);
-            if constexpr (k == 0)
-              acc[t] += P;
-            else
-              acc[t] = fma_r(xp[k], P, acc[t]);
-          });
-        });
-      }
-    });
-  }
-
-  // adjoint: sum over this chunk's monomials of g_t * monomial (Horner in x)
-  template <typename GetG>
-  static __device__ __forceinline__ Real poly(Real x, Real y, Real z, GetG&& g) {
-    Real total = Real(0);
-    Real zq = Real(1);
-    static_for<kDeg + 1>([&](auto qc) {
-      constexpr int q = decltype(qc)::value;
-      if constexpr (q > 0) zq = zq * z;
-      if constexpr (((QMASK >> q) & 1u) != 0) {
-        Real ysum = Real(0);  // sum_p y^p * (sum_k g x^k), Horner in y
-        static_for<kDeg + 1 - q>([&](auto pr) {
-          constexpr int p = kDeg - q - decltype(pr)::value;
-          Real hx = Real(0);
-          static_for<kDeg + 1 - q - p>([&](auto kr) {
-            constexpr int k = kDeg - q - p - decltype(kr)::value;
-            hx = fma_r(hx, x, g(cart_index_c(k, p, q)));
-          });
-          ysum = fma_r(ysum, y, hx);
-        });
-        total = fma_r(ysum, zq, total);
-      }
-    });
-    return total;
-  }
-
-  template <typename Store>
-  __device__ __forceinline__ void for_each_term(Store&& st) {
-    static_for<kDeg + 1>([&](auto qc) {
-      constexpr int q = decltype(qc)::value;
-      if constexpr (((QMASK >> q) & 1u) != 0) {
-        static_for<kDeg + 1 - q>([&](auto pc) {
-          constexpr int p = decltype(pc)::value;
-          static_for<kDeg + 1 - q - p>([&](auto kc) {
-            constexpr int k = decltype(kc)::value;
-            st(acc[cart_local(QMASK, k, p, q)], cart_index_c(k, p, q));
-          });
-        });
-      }
-    });
-  }
-};
-
-__host__ __device__ constexpr int spin_count(int m0, int m1) {
-  int c = 0;
-  for (int m = m0; m <= m1; ++m) c += (m == 0) ? (kDeg + 1) : 2 * (kDeg + 1 - m);
-  return c;
-}
-__host__ __device__ constexpr int spin_local(int m0, int m, int n, int part) {
-  int t = 0;
-  for (int mm = m0; mm < m; ++mm) t += (mm == 0) ? (kDeg + 1) : 2 * (kDeg + 1 - mm);
-  return (m == 0) ? t + n : t + 2 * n + part;
-}
-
-// Spin chunk: S_{m,n} = sum w (u_x - i u_y)^m u_z^n for M0 <= m <= M1.
-template <typename Real, int M0, int M1>
-struct SpinChunk {
-  static constexpr int NT = spin_count(M0, M1);
-  Real acc[NT];
-
-  __device__ __forceinline__ void zero() {
-#pragma unroll
-    for (int i = 0; i < NT; ++i) acc[i] = Real(0);
-  }
-
-  __device__ __forceinline__ void add(Real x, Real y, Real z, Real w) {
-    constexpr int NMAX = kDeg - (M0 > 0 ? M0 : 0);
-    Real zn[kDeg + 1];
-    zn[0] = Real(1);
-#pragma unroll
-    for (int n = 1; n <= NMAX; ++n) zn[n] = zn[n - 1] * z;
-    if constexpr (M0 == 0) {
-      acc[spin_local(M0, 0, 0, 0)] += w;
-      static_for<kDeg>([&](auto nc) {
-        constexpr int n = decltype(nc)::value + 1;
-        acc[spin_local(M0, 0, n, 0)] = fma_r(w, zn[n], acc[spin_local(M0, 0, n, 0)]);
-      });
-    }
-    if constexpr (M1 >= 1) {
-      Real cr = w * x, ci = -(w * y);  // w (x - i y)
-      static_for<M1>([&](auto mc) {
-        constexpr int m = decltype(mc)::value + 1;
-        if constexpr (m > 1) {
-          const Real nr = fma_r(cr, x, ci * y);
-          const Real ni = fma_r(ci, x, -(cr * y));
-          cr = nr;
-          ci = ni;
-        }
-        if constexpr (m >= M0) {
-          acc[spin_local(M0, m, 0, 0)] += cr;
-          acc[spin_local(M0, m, 0, 1)] += ci;
-          static_for<kDeg - m>([&](auto nc) {
-            constexpr int n = decltype(nc)::value + 1;
-            acc[spin_local(M0, m, n, 0)] = fma_r(cr, zn[n], acc[spin_local(M0, m, n, 0)]);
-            acc[spin_local(M0, m, n, 1)] = fma_r(ci, zn[n], acc[spin_local(M0, m, n, 1)]);
-          });
-        }
-      });
-    }
-  }
-
-  // adjoint: sum over this chunk of g_t * Re/Im parts of (x - i y)^m z^n
-  template <typename GetG>
-  static __device__ __forceinline__ Real poly(Real x, Real y, Real z, GetG&& g) {
-    Real total = Real(0);
-    Real cr = Real(1), ci = Real(0);
-    static_for<M1 + 1>([&](auto mc) {
-      constexpr int m = decltype(mc)::value;
-      if constexpr (m > 0) {
-        const Real nr = fma_r(cr, x, ci * y);
-        const Real ni = fma_r(ci, x, -(cr * y));
-        cr = nr;
-        ci = ni;
-      }
-      if constexpr (m >= M0) {
-        // Horner in z over n for the Re and Im coefficient sets
-        Real hr = Real(0), hi = Real(0);
-        static_for<kDeg - m + 1>([&](auto nr_) {
-          constexpr int n = kDeg - m - decltype(nr_)::value;
-          hr = fma_r(hr, z, g(spin_index_c(m, n, 0)));
-          if constexpr (m > 0) hi = fma_r(hi, z, g(spin_index_c(m, n, 1)));
-        });
-        if constexpr (m == 0)
-          total += hr;
-        else
-          total = fma_r(cr, hr, fma_r(ci, hi, total));
-      }
-    });
-    return total;
-  }
-
-  template <typename Store>
-  __device__ __forceinline__ void for_each_term(Store&& st) {
-    static_for<M1 - M0 + 1>([&](auto mc) {
-      constexpr int m = decltype(mc)::value + M0;
-      static_for<kDeg - m + 1>([&](auto nc) {
-        constexpr int n = decltype(nc)::value;
-        st(acc[spin_local(M0, m, n, 0)], spin_index_c(m, n, 0));
-        if constexpr (m > 0) st(acc[spin_local(M0, m, n, 1)], spin_index_c(m, n, 1));
-      });
-    });
-  }
-};
-
-template <class... C>
-struct ChunkList {};
-
-// Chunking keeps each chunk's accumulators within the 256 architected VGPRs.
-template <typename Real, int BASIS>
-struct Chunks;
-template <>
-struct Chunks<float, G3PCF_BASIS_CARTESIAN> {
-  using type = ChunkList<CartChunk<float, 0x023u>, CartChunk<float, 0x7DCu>>;
-};
-template <>
-struct Chunks<double, G3PCF_BASIS_CARTESIAN> {
-  using type = ChunkList<CartChunk<double, 0x601u>, CartChunk<double, 0x182u>,
-                         CartChunk<double, 0x00Cu>, CartChunk<double, 0x070u>>;
-};
-template <>
-struct Chunks<float, G3PCF_BASIS_SPIN> {
-  using type = ChunkList<SpinChunk<float, 0, kDeg>>;
-};
-template <>
-struct Chunks<double, G3PCF_BASIS_SPIN> {
-  using type = ChunkList<SpinChunk<double, 0, 3>, SpinChunk<double, 4, kDeg>>;
-};
-
-template <class... C, typename F>
-__device__ __forceinline__ void for_each_chunk(ChunkList<C...>, F&& f) {
-  (f(static_cast<C*>(nullptr)), ...);
-}
-
 // ---------------------------------------------------------------- per-wave LDS
 template <typename Real>
 struct WaveLds {
   int cnt[kMaxBins];
   int cur[kMaxBins];
   int off[kMaxBins];
-  Real M[kTermsCart];
+  int nseg;
+  int seg_g0[kMaxSegments];
+  int seg_g1[kMaxSegments];
+  int seg_code[kMaxSegments];  // image shift (kx+1) + 3 (ky+1) + 9 (kz+1)
+  Real M[kTermsCart + 1];      // reduced monomial sums (+1 padding slot)
 };
 
 constexpr int kWavesPerBlock = 4;
+constexpr int kUnroll = 4;  // candidate loads in flight per lane
 
 __device__ __forceinline__ void wave_lds_fence() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ int lanes_below(unsigned long long m) {
+  return __builtin_amdgcn_mbcnt_hi(unsigned(m >> 32), __builtin_amdgcn_mbcnt_lo(unsigned(m), 0));
 }
 
 // ---------------------------------------------------------------- candidate search
@@ -392,7 +92,7 @@ __device__ __forceinline__ double axis_box_dist(double p, int c_u, int nc, doubl
     return best;
   }
   double a = lo + c_u * s, b = a + s;
-  if (!periodic) {
+  if (!periodic) {  // the outer cells also hold any point beyond the box
     if (c_u == 0) a = -1e300;
     if (c_u == nc - 1) b = 1e300;
   }
@@ -409,14 +109,16 @@ __device__ __forceinline__ int cell_floor(double x, double lo, double inv_s) {
   return int(floor((x - lo) * inv_s));
 }
 
-// Visit every run of candidate galaxies for a primary at p (search radius R):
-// seg(g0, g1, sx, sy, sz) with the image shift of the run.
-template <typename SegF>
-__device__ __forceinline__ void for_each_segment(const PairArgs& a, const int* __restrict__ cs,
-                                                 const double p[3], SegF&& seg) {
+// Table of candidate runs of a primary at p: one lane per (cy, cz) row of
+// cells within reach; each row contributes one or two contiguous runs of
+// galaxies (two where the x window wraps around a periodic box).
+template <typename Real>
+__device__ __forceinline__ void build_segments(const PairArgs& a, const int* __restrict__ cs,
+                                               const double p[3], WaveLds<Real>& W) {
+  const int lane = threadIdx.x % kWave;
   const double R = a.rmax_search;
   int c0[3], c1[3];
-  for (int ax = 0; ax < 3; ++ax) {
+  for (int ax = 1; ax < 3; ++ax) {
     if (a.tight[ax]) {
       c0[ax] = 0;
       c1[ax] = a.nc[ax] - 1;
@@ -430,59 +132,85 @@ __device__ __forceinline__ void for_each_segment(const PairArgs& a, const int* _
     }
   }
   const int nx = a.nc[0], ny = a.nc[1], nz = a.nc[2];
-  for (int czu = c0[2]; czu <= c1[2]; ++czu) {
-    const double dz = axis_box_dist(p[2], czu, nz, a.lo[2], a.s[2], a.periodic, a.tight[2], a.L[2]);
-    if (dz >= R) continue;
-    int cz = czu;
-    double sz = 0.0;
-    if (a.periodic && !a.tight[2]) {
-      const int k = floor_div(czu, nz);
-      cz = czu - k * nz;
-      sz = k * a.L[2];
-    }
-    for (int cyu = c0[1]; cyu <= c1[1]; ++cyu) {
+  const int nyr = c1[1] - c0[1] + 1, nzr = c1[2] - c0[2] + 1;
+  const int nrows = nyr * nzr;
+  int nseg = 0;
+  for (int rb = 0; rb < nrows; rb += kWave) {
+    const int r = rb + lane;
+    int n_here = 0;
+    int g0a = 0, g1a = 0, ca = 0, g0b = 0, g1b = 0, cb = 0;
+    if (r < nrows) {
+      const int czu = c0[2] + r / nyr, cyu = c0[1] + r % nyr;
+      const double dz =
+          axis_box_dist(p[2], czu, nz, a.lo[2], a.s[2], a.periodic, a.tight[2], a.L[2]);
       const double dy =
           axis_box_dist(p[1], cyu, ny, a.lo[1], a.s[1], a.periodic, a.tight[1], a.L[1]);
       const double d2 = dy * dy + dz * dz;
-      if (d2 >= R * R) continue;
-      int cy = cyu;
-      double sy = 0.0;
-      if (a.periodic && !a.tight[1]) {
-        const int k = floor_div(cyu, ny);
-        cy = cyu - k * ny;
-        sy = k * a.L[1];
-      }
-      const int row = (cz * ny + cy) * nx;
-      if (a.tight[0]) {
-        const int g0 = cs[row], g1 = cs[row + nx];
-        if (g1 > g0) seg(g0, g1, 0.0, sy, sz);
-        continue;
-      }
-      const double hx = sqrt(R * R - d2);
-      int x0 = cell_floor(p[0] - hx, a.lo[0], a.inv_s[0]);
-      int x1 = cell_floor(p[0] + hx, a.lo[0], a.inv_s[0]);
-      if (!a.periodic) {
-        x0 = min(max(x0, 0), nx - 1);
-        x1 = min(max(x1, 0), nx - 1);
-        const int g0 = cs[row + x0], g1 = cs[row + x1 + 1];
-        if (g1 > g0) seg(g0, g1, 0.0, sy, sz);
-        continue;
-      }
-      const int k0 = floor_div(x0, nx);
-      const int a0 = x0 - k0 * nx;
-      const int b0 = x1 - k0 * nx;
-      if (b0 < nx) {
-        const int g0 = cs[row + a0], g1 = cs[row + b0 + 1];
-        if (g1 > g0) seg(g0, g1, k0 * a.L[0], sy, sz);
-      } else {
-        int g0 = cs[row + a0], g1 = cs[row + nx];
-        if (g1 > g0) seg(g0, g1, k0 * a.L[0], sy, sz);
-        g0 = cs[row];
-        g1 = cs[row + (b0 - nx) + 1];
-        if (g1 > g0) seg(g0, g1, (k0 + 1) * a.L[0], sy, sz);
+      if (d2 < R * R) {
+        int cz = czu, cy = cyu, kz = 0, ky = 0;
+        if (a.periodic && !a.tight[2]) {
+          kz = floor_div(czu, nz);
+          cz = czu - kz * nz;
+        }
+        if (a.periodic && !a.tight[1]) {
+          ky = floor_div(cyu, ny);
+          cy = cyu - ky * ny;
+        }
+        const int row = (cz * ny + cy) * nx;
+        const int cyz = 3 * (ky + 1) + 9 * (kz + 1);
+        if (a.tight[0]) {
+          g0a = cs[row];
+          g1a = cs[row + nx];
+          ca = 1 + cyz;
+          n_here = 1;
+        } else {
+          const double hx = sqrt(R * R - d2);
+          int x0 = cell_floor(p[0] - hx, a.lo[0], a.inv_s[0]);
+          int x1 = cell_floor(p[0] + hx, a.lo[0], a.inv_s[0]);
+          if (!a.periodic) {
+            x0 = min(max(x0, 0), nx - 1);
+            x1 = min(max(x1, 0), nx - 1);
+            g0a = cs[row + x0];
+            g1a = cs[row + x1 + 1];
+            ca = 1 + cyz;
+            n_here = 1;
+          } else {
+            const int k0 = floor_div(x0, nx);
+            const int a0 = x0 - k0 * nx, b0 = x1 - k0 * nx;
+            if (b0 < nx) {
+              g0a = cs[row + a0];
+              g1a = cs[row + b0 + 1];
+              ca = (k0 + 1) + cyz;
+              n_here = 1;
+            } else {
+              g0a = cs[row + a0];
+              g1a = cs[row + nx];
+              ca = (k0 + 1) + cyz;
+              g0b = cs[row];
+              g1b = cs[row + (b0 - nx) + 1];
+              cb = (k0 + 2) + cyz;
+              n_here = 2;
+            }
+          }
+        }
       }
     }
+    const unsigned long long m1 = __ballot(n_here >= 1), m2 = __ballot(n_here >= 2);
+    const int at = nseg + lanes_below(m1) + lanes_below(m2);
+    if (n_here >= 1 && at < kMaxSegments) {
+      W.seg_g0[at] = g0a;
+      W.seg_g1[at] = g1a;
+      W.seg_code[at] = ca;
+    }
+    if (n_here >= 2 && at + 1 < kMaxSegments) {
+      W.seg_g0[at + 1] = g0b;
+      W.seg_g1[at + 1] = g1b;
+      W.seg_code[at + 1] = cb;
+    }
+    nseg += __popcll(m1) + __popcll(m2);
   }
+  if (lane == 0) W.nseg = min(nseg, kMaxSegments);
+  wave_lds_fence();
 }
 
 // Separation, acceptance and shell of one candidate (identical in both passes).
@@ -522,7 +250,8 @@ __device__ __forceinline__ int PairTest<double>::bin_of(const double4& q) const 
   double d[3] = {__dsub_rn(q.x, ref[0]), __dsub_rn(q.y, ref[1]), __dsub_rn(q.z, ref[2])};
   if (minimg) {
     // L * k is exact for k in {-1, 0, 1}, so one rounding as in the definition
-    for (int c = 0; c < 3; ++c) d[c] = __dsub_rn(d[c], __dmul_rn(L[c], rint(__ddiv_rn(d[c], L[c]))));
+    for (int c = 0; c < 3; ++c)
+      d[c] = __dsub_rn(d[c], __dmul_rn(L[c], rint(__ddiv_rn(d[c], L[c]))));
   }
   const double r2 = __dadd_rn(__dadd_rn(__dmul_rn(d[0], d[0]), __dmul_rn(d[1], d[1])),
                               __dmul_rn(d[2], d[2]));
@@ -532,10 +261,50 @@ __device__ __forceinline__ int PairTest<double>::bin_of(const double4& q) const 
   return b < nbins ? b : nbins - 1;
 }
 
+// Occupancy target per kernel (waves per SIMD); the register budget is
+// 512 / target per lane, so every accumulator chunk must fit.
+template <typename Real, int BASIS, bool ADJOINT>
+struct Occ {
+  static constexpr int value =
+      ADJOINT ? 3 : ((std::is_same<Real, float>::value && BASIS == G3PCF_BASIS_SPIN) ? 3 : 2);
+};
+
 // ---------------------------------------------------------------- the kernel
 template <typename Real, int BASIS, bool ADJOINT>
 struct PairKernel {
   using V = typename V4<Real>::T;
+
+  // All lanes visit every candidate of the segment table; f(j, bin) is called
+  // by every lane (bin = -1 for a rejected or absent candidate).
+  template <typename F>
+  static __device__ __forceinline__ void scan(const PairArgs& a, const WaveLds<Real>& W,
+                                              const V* __restrict__ pos4, const double p[3],
+                                              PairTest<Real>& T, F&& f) {
+    const int lane = threadIdx.x % kWave;
+    const int nseg = uniform_int(W.nseg);
+    for (int s = 0; s < nseg; ++s) {
+      const int g0 = uniform_int(W.seg_g0[s]), g1 = uniform_int(W.seg_g1[s]);
+      if (g1 <= g0) continue;
+      if (!T.minimg) {
+        const int code = uniform_int(W.seg_code[s]);
+        const int kx = code % 3 - 1, ky = (code / 3) % 3 - 1, kz = code / 9 - 1;
+        T.ref[0] = Real(p[0] - kx * a.L[0]);
+        T.ref[1] = Real(p[1] - ky * a.L[1]);
+        T.ref[2] = Real(p[2] - kz * a.L[2]);
+      }
+      for (int base = g0; base < g1; base += kUnroll * kWave) {
+        V q[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) q[u] = pos4[min(base + u * kWave + lane, g1 - 1)];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const int j = base + u * kWave + lane;
+          const int b = (j < g1) ? T.bin_of(q[u]) : -1;
+          f(j, b);
+        }
+      }
+    }
+  }
 
   static __device__ __forceinline__ void run(const PairArgs& a) {
     extern __shared__ char smem_raw[];
@@ -595,6 +364,7 @@ struct PairKernel {
       for (int c = 0; c < 3; ++c) {
         T.L[c] = Real(a.L[c]);
         T.invL[c] = Real(1.0 / a.L[c]);
+        T.ref[c] = Real(p[c]);
       }
       T.minimg = a.periodic && (std::is_same<Real, double>::value || a.tight[0] || a.tight[1] ||
                                 a.tight[2]);
@@ -602,30 +372,13 @@ struct PairKernel {
       T.nb_over_r = Real(double(nb) / a.rmax);
       T.nbins = nb;
       T.rmax_d = a.rmax;
-      auto set_ref = [&](double sx, double sy, double sz) {
-        if (T.minimg) {
-          T.ref[0] = Real(p[0]);
-          T.ref[1] = Real(p[1]);
-          T.ref[2] = Real(p[2]);
-        } else {
-          T.ref[0] = Real(p[0] - sx);
-          T.ref[1] = Real(p[1] - sy);
-          T.ref[2] = Real(p[2] - sz);
-        }
-      };
 
-      // ---- pass 1: count accepted secondaries per shell
+      // ---- pass 0: candidate runs; pass 1: count accepted secondaries per shell
+      build_segments(a, cs, p, W);
       if (lane < nb) W.cnt[lane] = 0;
       wave_lds_fence();
-      for_each_segment(a, cs, p, [&](int g0, int g1, double sx, double sy, double sz) {
-        set_ref(sx, sy, sz);
-        for (int base = g0; base < g1; base += kWave) {
-          const int j = base + lane;
-          if (j < g1) {
-            const int b = T.bin_of(pos4[j]);
-            if (b >= 0) atomicAdd(&W.cnt[b], 1);
-          }
-        }
+      scan(a, W, pos4, p, T, [&](int, int b) {
+        if (b >= 0) atomicAdd(&W.cnt[b], 1);
       });
       wave_lds_fence();
 
@@ -634,8 +387,6 @@ struct PairKernel {
       my_pairs += (unsigned long long)total;
 
       const long long row = q;  // row of A within this pair-block
-
-      // adjoint: primary weight
       double w_prim = 0.0;
       if constexpr (ADJOINT) w_prim = a.wsort[slot];
 
@@ -644,7 +395,7 @@ struct PairKernel {
       while (b < nb) {
         const int cb = uniform_int(W.cnt[b]);
         if (cb > S) {
-          process_sliced(a, W, scratch, pos4, cs, p, T, set_ref, Rm, b, cb, row, slot, w_prim);
+          process_sliced(a, W, scratch, pos4, p, T, Rm, b, cb, row, w_prim);
           ++b;
           continue;
         }
@@ -662,17 +413,10 @@ struct PairKernel {
         wave_lds_fence();
         if (tot > 0) {
           const int gb0 = b, gb1 = e;
-          for_each_segment(a, cs, p, [&](int g0, int g1, double sx, double sy, double sz) {
-            set_ref(sx, sy, sz);
-            for (int base = g0; base < g1; base += kWave) {
-              const int j = base + lane;
-              if (j < g1) {
-                const int bb = T.bin_of(pos4[j]);
-                if (bb >= gb0 && bb < gb1) {
-                  const int at = atomicAdd(&W.cur[bb], 1);
-                  if (at < W.cnt[bb]) scratch[W.off[bb] + at] = j;
-                }
-              }
+          scan(a, W, pos4, p, T, [&](int j, int bb) {
+            if (bb >= gb0 && bb < gb1) {
+              const int at = atomicAdd(&W.cur[bb], 1);
+              if (at < W.cnt[bb]) scratch[W.off[bb] + at] = j;
             }
           });
           wave_lds_fence();
@@ -680,37 +424,32 @@ struct PairKernel {
         for (int bb = b; bb < e; ++bb) {
           const int cbb = uniform_int(W.cnt[bb]);
           const int* list = scratch + uniform_int(W.off[bb]);
-          shell(a, W, pos4, p, Rm, bb, list, cbb, row, slot, w_prim);
+          shell(a, W, pos4, p, Rm, bb, list, cbb, row, w_prim);
         }
         b = e;
       }
     }
 
-    // pairs counted once per primary by lane 0
     if (lane == 0 && my_pairs) atomicAdd(a.pairs, my_pairs);
   }
 
-  // Unit separation (rotated) and weight of list entry i (w = 0 past the end).
-  static __device__ __forceinline__ void load_pair(const PairArgs& a, const V* __restrict__ pos4,
-                                                   const double p[3], const Real* Rm,
-                                                   const int* __restrict__ list, int count,
-                                                   int i, Real& ux, Real& uy, Real& uz,
-                                                   Real& w, int& j) {
-    const bool valid = i < count;
-    j = valid ? list[i] : -1;
-    Real dx = Real(0), dy = Real(0), dz = Real(1);
-    w = Real(0);
-    if (valid) {
-      const V qv = pos4[j];
-      dx = qv.x - Real(p[0]);
-      dy = qv.y - Real(p[1]);
-      dz = qv.z - Real(p[2]);
-      if (a.periodic) {
-        dx -= Real(a.L[0]) * rint(dx * Real(1.0 / a.L[0]));
-        dy -= Real(a.L[1]) * rint(dy * Real(1.0 / a.L[1]));
-        dz -= Real(a.L[2]) * rint(dz * Real(1.0 / a.L[2]));
-      }
-      w = qv.w;
+  // Unit separation (rotated) and weight from a loaded secondary.
+  static __device__ __forceinline__ void unit_pair(const PairArgs& a, const V& qv, bool valid,
+                                                   const double p[3], const Real* Rm, Real& ux,
+                                                   Real& uy, Real& uz, Real& w) {
+    Real dx = qv.x - Real(p[0]);
+    Real dy = qv.y - Real(p[1]);
+    Real dz = qv.z - Real(p[2]);
+    if (a.periodic) {
+      dx -= Real(a.L[0]) * rint(dx * Real(1.0 / a.L[0]));
+      dy -= Real(a.L[1]) * rint(dy * Real(1.0 / a.L[1]));
+      dz -= Real(a.L[2]) * rint(dz * Real(1.0 / a.L[2]));
+    }
+    w = valid ? qv.w : Real(0);
+    if (!valid) {
+      dx = Real(0);
+      dy = Real(0);
+      dz = Real(1);
     }
     Real inv;
     if constexpr (std::is_same<Real, float>::value) {
@@ -732,42 +471,56 @@ struct PairKernel {
     }
   }
 
-  // Forward: accumulate one chunk over a list of pairs.
-  template <class Chunk>
-  static __device__ __forceinline__ void accumulate(const PairArgs& a, const V* __restrict__ pos4,
-                                                    const double p[3], const Real* Rm,
-                                                    const int* __restrict__ list, int count,
-                                                    Chunk& ch) {
+  // Stream a list with the gather of the next pair and the index two pairs
+  // ahead already in flight; body(ux, uy, uz, w, j, valid) per lane.
+  template <typename Body>
+  static __device__ __forceinline__ void stream(const PairArgs& a, const V* __restrict__ pos4,
+                                                const double p[3], const Real* Rm,
+                                                const int* __restrict__ list, int count,
+                                                Body&& body) {
+    if (count <= 0) return;
     const int lane = threadIdx.x % kWave;
+    const int last = count - 1;
+    int j0 = list[min(lane, last)];
+    int j1 = list[min(kWave + lane, last)];
+    V q0 = pos4[j0];
     for (int base = 0; base < count; base += kWave) {
+      const V qc = q0;
+      const int jc = j0;
+      const bool valid = base + lane < count;
+      q0 = pos4[j1];
+      j0 = j1;
+      j1 = list[min(base + 2 * kWave + lane, last)];
       Real ux, uy, uz, w;
-      int j;
-      load_pair(a, pos4, p, Rm, list, count, base + lane, ux, uy, uz, w, j);
-      ch.add(ux, uy, uz, w);
+      unit_pair(a, qc, valid, p, Rm, ux, uy, uz, w);
+      body(ux, uy, uz, w, jc, valid);
     }
   }
 
+  // Wave sums of a chunk's accumulators into W.M, four at a time: row sums by
+  // DPP, then one fold across rows leaves the four totals in rows 0..3, and
+  // every lane stores its row's total (16 lanes write the same value).
   template <class Chunk>
   static __device__ __forceinline__ void reduce_store(WaveLds<Real>& W, Chunk& ch) {
-    const int lane = threadIdx.x % kWave;
-    ch.for_each_term([&](Real& v, int) { v = wave_sum(v); });
-    if (lane == kWave - 1) ch.for_each_term([&](Real& v, int t) { W.M[t] = v; });
-  }
-
-  // Adjoint: sum_t g_t mono_t(u) over a chunk for a list, scattered into grad.
-  template <class Chunk>
-  static __device__ __forceinline__ void scatter(const PairArgs& a, const V* __restrict__ pos4,
-                                                 const double p[3], const Real* Rm,
-                                                 const int* __restrict__ list, int count,
-                                                 const WaveLds<Real>& W, double w_prim) {
-    const int lane = threadIdx.x % kWave;
-    for (int base = 0; base < count; base += kWave) {
-      Real ux, uy, uz, w;
-      int j;
-      load_pair(a, pos4, p, Rm, list, count, base + lane, ux, uy, uz, w, j);
-      const Real v = Chunk::poly(ux, uy, uz, [&](int t) { return W.M[t]; });
-      if (j >= 0) unsafeAtomicAdd(&a.grad_w[j], w_prim * double(v));
-    }
+    constexpr int NT = Chunk::NT;
+    constexpr int kJunk = kTermsCart;  // slot that absorbs padding in the last group
+    const int row = (threadIdx.x % kWave) >> 4;
+    static_for<(NT + 3) / 4>([&](auto gc) {
+      constexpr int g = decltype(gc)::value;
+      constexpr int i0 = 4 * g, i1 = 4 * g + 1, i2 = 4 * g + 2, i3 = 4 * g + 3;
+      const Real a = row_sum(ch.acc[i0]);
+      Real e = Real(0), b = Real(0), f = Real(0);
+      if constexpr (i1 < NT) e = row_sum(ch.acc[i1]);
+      if constexpr (i2 < NT) b = row_sum(ch.acc[i2]);
+      if constexpr (i3 < NT) f = row_sum(ch.acc[i3]);
+      const Real tot = fold4(a, e, b, f);
+      constexpr int ta = Chunk::term_of(i0);
+      constexpr int te = (i1 < NT) ? Chunk::term_of(i1) : kJunk;
+      constexpr int tb = (i2 < NT) ? Chunk::term_of(i2) : kJunk;
+      constexpr int tf = (i3 < NT) ? Chunk::term_of(i3) : kJunk;
+      const int t = row == 0 ? ta : (row == 1 ? te : (row == 2 ? tb : tf));
+      W.M[t] = tot;
+    });
   }
 
   // Convert the shell's monomial sums in W.M to a_lm (FP64) and write them.
@@ -788,29 +541,63 @@ struct PairKernel {
     }
   }
 
-  template <typename SetRef>
-  static __device__ void process_sliced(const PairArgs& a, WaveLds<Real>& W, int* scratch,
-                                        const V* __restrict__ pos4, const int* __restrict__ cs,
-                                        const double p[3], PairTest<Real>& T, SetRef& set_ref,
-                                        const Real* Rm, int b, int cb, long long row, int slot,
-                                        double w_prim) {
+  static __device__ __forceinline__ void load_gcoef(const PairArgs& a, WaveLds<Real>& W, int b,
+                                                    long long row) {
     const int lane = threadIdx.x % kWave;
+    constexpr int T = (BASIS == G3PCF_BASIS_SPIN) ? kTermsSpin : kTermsCart;
+    const double* g = a.gcoef + (row * a.nbins + b) * T;
+    for (int t = lane; t < T; t += kWave) W.M[t] = Real(g[t]);
+    wave_lds_fence();
+  }
+
+  // Forward: all chunks of one shell from a list, then conversion.
+  static __device__ __forceinline__ void shell(const PairArgs& a, WaveLds<Real>& W,
+                                               const V* __restrict__ pos4, const double p[3],
+                                               const Real* Rm, int b, const int* list,
+                                               int count, long long row, double w_prim) {
+    using CL = typename Chunks<Real, BASIS>::type;
+    if constexpr (!ADJOINT) {
+      for_each_chunk(CL{}, [&](auto* tag) {
+        using Chunk = std::remove_pointer_t<decltype(tag)>;
+        Chunk ch;
+        ch.zero();
+        stream(a, pos4, p, Rm, list, count,
+               [&](Real ux, Real uy, Real uz, Real w, int, bool) { ch.add(ux, uy, uz, w); });
+        reduce_store(W, ch);
+      });
+      wave_lds_fence();
+      convert(a, W, b, row);
+      wave_lds_fence();
+    } else {
+      if (count == 0) return;
+      load_gcoef(a, W, b, row);
+      for_each_chunk(CL{}, [&](auto* tag) {
+        using Chunk = std::remove_pointer_t<decltype(tag)>;
+        stream(a, pos4, p, Rm, list, count,
+               [&](Real ux, Real uy, Real uz, Real, int j, bool valid) {
+                 const Real v = Chunk::poly(ux, uy, uz, [&](int t) { return W.M[t]; });
+                 if (valid) unsafeAtomicAdd(&a.grad_w[j], w_prim * double(v));
+               });
+      });
+      wave_lds_fence();
+    }
+  }
+
+  // A shell with more pairs than the scratch holds: slices of S pairs in a
+  // deterministic order (ballot ranks), the search repeated per slice.
+  static __device__ void process_sliced(const PairArgs& a, WaveLds<Real>& W, int* scratch,
+                                        const V* __restrict__ pos4, const double p[3],
+                                        PairTest<Real>& T, const Real* Rm, int b, int cb,
+                                        long long row, double w_prim) {
     const int S = a.scratch_per_wave;
-    // fill one slice [s0, s0 + S) of shell b with deterministic ranks
     auto fill_slice = [&](int s0) {
       int rank_base = 0;
-      for_each_segment(a, cs, p, [&](int g0, int g1, double sx, double sy, double sz) {
-        set_ref(sx, sy, sz);
-        for (int base = g0; base < g1; base += kWave) {
-          const int j = base + lane;
-          const bool hit = (j < g1) && (T.bin_of(pos4[j]) == b);
-          const unsigned long long m = __ballot(hit);
-          const int r = rank_base + __builtin_amdgcn_mbcnt_hi(
-                                        unsigned(m >> 32),
-                                        __builtin_amdgcn_mbcnt_lo(unsigned(m), 0));
-          if (hit && r >= s0 && r < s0 + S) scratch[r - s0] = j;
-          rank_base += __popcll(m);
-        }
+      scan(a, W, pos4, p, T, [&](int j, int bb) {
+        const bool hit = (bb == b);
+        const unsigned long long m = __ballot(hit);
+        const int r = rank_base + lanes_below(m);
+        if (hit && r >= s0 && r < s0 + S) scratch[r - s0] = j;
+        rank_base += __popcll(m);
       });
       wave_lds_fence();
     };
@@ -822,66 +609,36 @@ struct PairKernel {
         ch.zero();
         for (int s0 = 0; s0 < cb; s0 += S) {
           fill_slice(s0);
-          accumulate(a, pos4, p, Rm, scratch, min(S, cb - s0), ch);
+          stream(a, pos4, p, Rm, scratch, min(S, cb - s0),
+                 [&](Real ux, Real uy, Real uz, Real w, int, bool) { ch.add(ux, uy, uz, w); });
         }
         reduce_store(W, ch);
       });
       wave_lds_fence();
       convert(a, W, b, row);
+      wave_lds_fence();
     } else {
       load_gcoef(a, W, b, row);
       for (int s0 = 0; s0 < cb; s0 += S) {
         fill_slice(s0);
         for_each_chunk(CL{}, [&](auto* tag) {
           using Chunk = std::remove_pointer_t<decltype(tag)>;
-          scatter<Chunk>(a, pos4, p, Rm, scratch, min(S, cb - s0), W, w_prim);
+          stream(a, pos4, p, Rm, scratch, min(S, cb - s0),
+                 [&](Real ux, Real uy, Real uz, Real, int j, bool valid) {
+                   const Real v = Chunk::poly(ux, uy, uz, [&](int t) { return W.M[t]; });
+                   if (valid) unsafeAtomicAdd(&a.grad_w[j], w_prim * double(v));
+                 });
         });
       }
-    }
-    (void)slot;
-  }
-
-  static __device__ __forceinline__ void load_gcoef(const PairArgs& a, WaveLds<Real>& W, int b,
-                                                    long long row) {
-    const int lane = threadIdx.x % kWave;
-    constexpr int T = (BASIS == G3PCF_BASIS_SPIN) ? kTermsSpin : kTermsCart;
-    const double* g = a.gcoef + (row * a.nbins + b) * T;
-    for (int t = lane; t < T; t += kWave) W.M[t] = Real(g[t]);
-    wave_lds_fence();
-  }
-
-  static __device__ __forceinline__ void shell(const PairArgs& a, WaveLds<Real>& W,
-                                               const V* __restrict__ pos4, const double p[3],
-                                               const Real* Rm, int b, const int* list,
-                                               int count, long long row, int slot,
-                                               double w_prim) {
-    using CL = typename Chunks<Real, BASIS>::type;
-    if constexpr (!ADJOINT) {
-      for_each_chunk(CL{}, [&](auto* tag) {
-        using Chunk = std::remove_pointer_t<decltype(tag)>;
-        Chunk ch;
-        ch.zero();
-        accumulate(a, pos4, p, Rm, list, count, ch);
-        reduce_store(W, ch);
-      });
-      wave_lds_fence();
-      convert(a, W, b, row);
-      wave_lds_fence();
-    } else {
-      if (count == 0) return;
-      load_gcoef(a, W, b, row);
-      for_each_chunk(CL{}, [&](auto* tag) {
-        using Chunk = std::remove_pointer_t<decltype(tag)>;
-        scatter<Chunk>(a, pos4, p, Rm, list, count, W, w_prim);
-      });
       wave_lds_fence();
     }
-    (void)slot;
   }
 };
 
 template <typename Real, int BASIS, bool ADJOINT>
-__global__ __launch_bounds__(kWave* kWavesPerBlock) void k_pairs(PairArgs a) {
+__global__ __launch_bounds__(kWave* kWavesPerBlock)
+    __attribute__((amdgpu_waves_per_eu(Occ<Real, BASIS, ADJOINT>::value))) void k_pairs(
+        PairArgs a) {
   PairKernel<Real, BASIS, ADJOINT>::run(a);
 }
 
