@@ -63,6 +63,9 @@ def main():
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--sample", type=int, default=1024,
                     help="primaries in the seeded sample used for errors and the CPU baseline")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run one plain device copy of MIB MiB (reference for the "
+                         "FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -75,6 +78,15 @@ def main():
     from paper_1709_00086_amd import _lib, api, catalogues as C
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {args.copy_calibration} MiB read + written once")
+        del src, dst
     t = time.time()
     cat = getattr(C, WORKLOADS[args.workload])()
     log(f"workload {cat.name}: n={cat.n} generated in {time.time() - t:.1f}s")

@@ -7,6 +7,15 @@
 //   H_lm(b)  = U_lm(b) + conj(V_lm(b)),
 //   dL/dw_i (as a primary)            = Re sum_{lm, b} a_lm(b) U_lm(b),
 //   dL/dw_k (k a secondary in shell b) += w_i Re sum_lm conj(Y_lm(u_ik)) H_lm(b).
+//
+// For one m write x = [Re a | Im a] (the primary's block of its A row) and
+// G^m = Gr + i Gi over the (l, b) indices.  Then
+//   H = M_H x,  M_H = [[S, A], [A, -S]],  S = Gr + Gr^T,  A = Gi^T - Gi,
+// (for m = 0, x = Re a and only S is needed), and since
+// Re(a^T U) = Re(a^T conj(V)), the primary term is Re(a^T H) / 2.
+// So for a block of primaries H = X M_H^T per m: a GEMM of the same shapes as
+// the forward Gram products, run on FP64 MFMA.
+//
 // Because conj(Y_lm(u)) = sum_t c_{lm,t} mono_t(u) with the same monomials the
 // forward pass accumulates, the secondary term is a polynomial in u with
 // coefficients g_t(b) = sum_lm (Re c_{lm,t} Re H_lm(b) - Im c_{lm,t} Im H_lm(b)),
@@ -19,61 +28,127 @@ namespace g3 {
 
 namespace {
 
-constexpr int kAdjThreads = 256;
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kTile = 16;
 
 __device__ __forceinline__ size_t zidx(int lmax, int nb, int m, int l, int lp, int b1, int b2) {
   const size_t L1 = size_t(lmax) + 1;
   return ((((size_t(m) * L1 + l) * L1 + lp) * nb + b1) * nb + b2) * 2;
 }
 
-// one block per primary row of the pair-block
-__global__ __launch_bounds__(kAdjThreads) void k_adj_coef(AdjArgs a) {
-  extern __shared__ double sh[];
-  const RowLayout& L = a.lay;
-  const int nb = L.nb, lmax = L.lmax;
+struct AdjDims {
+  int nm;
+  int W[kDeg + 1], off[kDeg + 1], d[kDeg + 1];
+  int cw[kDeg + 2];     // offset of M_H^m in the matrix buffer
+  int ctiles[kDeg + 2]; // cumulative column tiles
+  int rowW, nb, lmax;
+};
+
+AdjDims make_adj_dims(const RowLayout& L) {
+  AdjDims d{};
+  d.nm = L.lmax + 1;
+  d.rowW = L.W;
+  d.nb = L.nb;
+  d.lmax = L.lmax;
+  int cw = 0, ct = 0;
+  for (int m = 0; m < d.nm; ++m) {
+    d.W[m] = L.wm[m];
+    d.off[m] = L.off[m];
+    d.d[m] = L.d[m];
+    d.cw[m] = cw;
+    d.ctiles[m] = ct;
+    cw += L.wm[m] * L.wm[m];
+    ct += (L.wm[m] + kTile - 1) / kTile;
+  }
+  d.cw[d.nm] = cw;
+  d.ctiles[d.nm] = ct;
+  return d;
+}
+
+// M_H^m stored transposed: MHt[cw_m + k * W_m + j] = M_H^m[j][k].
+__global__ void k_build_mh(const double* __restrict__ gz, AdjDims d, double* __restrict__ MHt) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= d.cw[d.nm]) return;
+  int m = 0;
+  while (m + 1 < d.nm && idx >= d.cw[m + 1]) ++m;
+  const int W = d.W[m], dm = d.d[m], nb = d.nb;
+  const int r = idx - d.cw[m];
+  const int k = r / W, j = r % W;  // entry M_H[j][k]
+  auto G = [&](int a, int b, int part) {  // G^m[a][b] over (l, b) indices
+    const int l = m + a / nb, b1 = a % nb, lp = m + b / nb, b2 = b % nb;
+    return gz[zidx(d.lmax, nb, m, l, lp, b1, b2) + part];
+  };
+  double v;
+  if (m == 0) {
+    v = G(j, k, 0) + G(k, j, 0);
+  } else {
+    const bool jr = j < dm, kr = k < dm;
+    const int jj = jr ? j : j - dm, kk = kr ? k : k - dm;
+    if (jr && kr) v = G(jj, kk, 0) + G(kk, jj, 0);            // S
+    else if (!jr && !kr) v = -(G(jj, kk, 0) + G(kk, jj, 0));  // -S
+    else v = G(kk, jj, 1) - G(jj, kk, 1);                     // A = Gi^T - Gi
+  }
+  MHt[idx] = v;
+}
+
+// H rows = X rows times M_H^T, per m, on FP64 MFMA.  One wave per
+// (16 primaries, m, 16 output columns).  Lane l supplies A[i = l % 16][k = l / 16]
+// = X[row i][k] and B[k = l / 16][j = l % 16] = M_H^T[k][j]; the FP64 result
+// holds row g + 4 r (g = l / 16) in register r.
+__global__ __launch_bounds__(256) void k_h_gemm(const double* __restrict__ A,
+                                                const double* __restrict__ MHt, AdjDims d,
+                                                long long rows, double* __restrict__ H) {
+  const long long wave = (long long)blockIdx.x * 4 + threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  const int nct = d.ctiles[d.nm];
+  const long long rt = wave / nct;
+  const int ct = int(wave % nct);
+  if (rt * kTile >= rows) return;
+  int m = 0;
+  while (m + 1 < d.nm && ct >= d.ctiles[m + 1]) ++m;
+  const int W = d.W[m];
+  const int j0 = (ct - d.ctiles[m]) * kTile;
+  const int il = lane % 16, g = lane / 16;
+  const long long r = rt * kTile + il;
+  const bool rv = r < rows;
+  const double* xrow = A + (rv ? r : 0) * (long long)d.rowW + d.off[m];
+  const double* B = MHt + d.cw[m];
+  const int j = j0 + il;
+  double4_t acc = {0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < W; k0 += 4) {
+    const int k = k0 + g;
+    const double av = (rv && k < W) ? xrow[k] : 0.0;
+    const double bv = (k < W && j < W) ? B[k * W + j] : 0.0;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+  }
+  for (int q = 0; q < 4; ++q) {
+    const long long rr = rt * kTile + g + 4 * q;
+    if (rr < rows && j < W) H[rr * d.rowW + d.off[m] + j] = acc[q];
+  }
+}
+
+// Per primary: the primary term Re(a^T H) / 2 and the coefficients g_t(b).
+constexpr int kFinThreads = 128;
+
+__global__ __launch_bounds__(kFinThreads) void k_adj_finish(AdjArgs a, AdjDims d) {
   const long long row = blockIdx.x;
   const long long valid = min(a.p_count, (long long)(*a.nprim) - a.p_begin);
   if (row >= valid) return;
   const int slot = a.plist[a.p_begin + row];
-  double* arow = sh;                 // [W]
-  double* H = sh + L.W;              // [nb][nlm][2]
-  __shared__ double red[kAdjThreads];
-  const int nlm = (lmax + 1) * (lmax + 2) / 2;
-  const double* A = a.A + row * (long long)L.W;
-  for (int c = threadIdx.x; c < L.W; c += blockDim.x) arow[c] = A[c];
-  __syncthreads();
-
-  auto a_re = [&](int l, int m, int b) { return arow[L.off[m] + (l - m) * nb + b]; };
-  auto a_im = [&](int l, int m, int b) {
-    return m == 0 ? 0.0 : arow[L.off[m] + L.d[m] + (l - m) * nb + b];
-  };
-
+  const double* x = a.A + row * (long long)d.rowW;
+  const double* h = a.H + row * (long long)d.rowW;
+  __shared__ double hs[4096];
+  __shared__ double red[kFinThreads];
   double prim = 0.0;
-  for (int o = threadIdx.x; o < nb * nlm; o += blockDim.x) {
-    const int b = o / nlm;
-    int lm = o % nlm;
-    int l = 0;
-    while ((l + 1) * (l + 2) / 2 <= lm) ++l;
-    const int m = lm - l * (l + 1) / 2;
-    double ur = 0.0, ui = 0.0, vr = 0.0, vi = 0.0;
-    for (int lp = m; lp <= lmax; ++lp)
-      for (int bb = 0; bb < nb; ++bb) {
-        // U += conj(G(m,l,lp,b,bb)) conj(a_lp,m(bb))
-        const double* g = a.gz + zidx(lmax, nb, m, l, lp, b, bb);
-        const double xr = a_re(lp, m, bb), xi = a_im(lp, m, bb);
-        // (gr - i gi)(xr - i xi) = gr xr - gi xi - i (gr xi + gi xr)
-        ur += g[0] * xr - g[1] * xi;
-        ui -= g[0] * xi + g[1] * xr;
-        // V += conj(G(m,lp,l,bb,b)) a_lp,m(bb)
-        const double* h = a.gz + zidx(lmax, nb, m, lp, l, bb, b);
-        // (hr - i hi)(xr + i xi) = hr xr + hi xi + i (hr xi - hi xr)
-        vr += h[0] * xr + h[1] * xi;
-        vi += h[0] * xi - h[1] * xr;
-      }
-    // primary term: Re(a U)
-    prim += a_re(l, m, b) * ur - a_im(l, m, b) * ui;
-    H[(b * nlm + lm) * 2] = ur + vr;
-    H[(b * nlm + lm) * 2 + 1] = ui - vi;
+  for (int c = threadIdx.x; c < d.rowW; c += blockDim.x) {
+    const double hv = h[c];
+    hs[c] = hv;
+    // column c belongs to block m; the imaginary half enters with a minus sign
+    int m = 0;
+    while (m + 1 < d.nm && c >= d.off[m + 1]) ++m;
+    const bool imag = (m > 0) && (c - d.off[m] >= d.d[m]);
+    prim += imag ? -x[c] * hv : x[c] * hv;
   }
   red[threadIdx.x] = prim;
   __syncthreads();
@@ -81,10 +156,10 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_coef(AdjArgs a) {
     if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }
-  if (threadIdx.x == 0) a.grad_w[slot] += red[0];
+  if (threadIdx.x == 0) a.grad_w[slot] += 0.5 * red[0];
 
-  // g_t(b) from the by-term table
   const ConvTable& t = *a.table;
+  const int nb = d.nb;
   const int T = (a.basis == G3PCF_BASIS_SPIN) ? kTermsSpin : kTermsCart;
   double* gout = a.gcoef + row * (long long)nb * T;
   for (int o = threadIdx.x; o < nb * T; o += blockDim.x) {
@@ -93,11 +168,10 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_coef(AdjArgs a) {
     for (int e = t.trowptr[term]; e < t.trowptr[term + 1]; ++e) {
       const int out = t.tout[e];
       const int l = t.out_l[out];
-      if (l > lmax) continue;
+      if (l > d.lmax) continue;
       const int m = t.out_m[out], part = t.out_part[out];
-      const int lm = l * (l + 1) / 2 + m;
-      const double* h = H + (b * nlm + lm) * 2;
-      s += (part == 0) ? t.tcoef[e] * h[0] : -t.tcoef[e] * h[1];
+      const int col = d.off[m] + (l - m) * nb + b;
+      s += (part == 0) ? t.tcoef[e] * hs[col] : -t.tcoef[e] * hs[col + d.d[m]];
     }
     gout[o] = s;
   }
@@ -113,10 +187,26 @@ __global__ void k_unpermute(const double* __restrict__ gs, const int* __restrict
 
 }  // namespace
 
+size_t adj_matrix_doubles(const RowLayout& L) { return size_t(sum_wm2(L)); }
+
+hipError_t launch_adj_matrix(const double* gz, const RowLayout& L, double* MHt,
+                             hipStream_t st) {
+  const AdjDims d = make_adj_dims(L);
+  const int n = d.cw[d.nm];
+  hipLaunchKernelGGL(k_build_mh, dim3((n + 255) / 256), dim3(256), 0, st, gz, d, MHt);
+  return hipGetLastError();
+}
+
 hipError_t launch_adj_coef(const AdjArgs& a, hipStream_t st) {
-  const int nlm = (a.lay.lmax + 1) * (a.lay.lmax + 2) / 2;
-  const size_t lds = sizeof(double) * (size_t(a.lay.W) + 2 * size_t(a.lay.nb) * nlm);
-  hipLaunchKernelGGL(k_adj_coef, dim3(unsigned(a.p_count)), dim3(kAdjThreads), lds, st, a);
+  const AdjDims d = make_adj_dims(a.lay);
+  if (d.rowW > 4096) return hipErrorInvalidValue;
+  const long long row_tiles = (a.p_count + kTile - 1) / kTile;
+  const long long waves = row_tiles * d.ctiles[d.nm];
+  hipLaunchKernelGGL(k_h_gemm, dim3(unsigned((waves + 3) / 4)), dim3(256), 0, st, a.A, a.MHt,
+                     d, a.p_count, a.H);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_adj_finish, dim3(unsigned(a.p_count)), dim3(kFinThreads), 0, st, a, d);
   return hipGetLastError();
 }
 

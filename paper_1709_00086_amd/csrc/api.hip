@@ -61,7 +61,7 @@ size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Ws {
   size_t pos4, tmp4, cid, perm, tmp_perm, wsort, cell_start, cell_count, flags, plist, scan,
-      counters, scratch, A, C, ops, gcoef, gsort;
+      counters, scratch, A, C, ops, gcoef, gsort, mht, hrows;
   size_t scan_bytes;
   size_t total;
   int64_t PB;   // primaries per pair-block
@@ -79,7 +79,7 @@ Ws plan(const g3pcf_problem& p, int backward) {
   w.grid = make_grid(p);
   w.lay = make_layout(p.lmax, p.nbins);
   const int64_t ncell = w.grid.ncell;
-  w.PB = std::max<int64_t>(1, std::min<int64_t>(n, backward ? 16384 : kPairBlockMax));
+  w.PB = std::max<int64_t>(1, std::min<int64_t>(n, kPairBlockMax));
   w.S = int(std::min<int64_t>(kScratchMax, std::max<int64_t>(64, (n + 63) / 64 * 64)));
   w.Kp = ((std::min<int64_t>(kZetaBlock, w.PB) + 31) / 32) * 32;
   w.scan_bytes = scan_tmp_bytes(std::max<int64_t>(ncell + 1, n + 1));
@@ -110,6 +110,8 @@ Ws plan(const g3pcf_problem& p, int backward) {
     const int T = (p.basis == G3PCF_BASIS_SPIN) ? kTermsSpin : kTermsCart;
     w.gcoef = take(size_t(w.PB) * p.nbins * T * 8);
     w.gsort = take(size_t(n) * 8);
+    w.mht = take(adj_matrix_doubles(w.lay) * 8);
+    w.hrows = take(size_t(w.PB) * w.lay.W * 8);
   }
   w.total = at;
   return w;
@@ -403,6 +405,11 @@ int g3pcf_backward(const g3pcf_problem* prob, const double* grad_zeta, double* g
   double* gsort = at<double>(ws, w.gsort);
   if ((e = launch_fill_double(gsort, p.n, 0.0, st)) != hipSuccess)
     return hip_fail(e, "gradient clear");
+  {
+    StageScope sc(p.trace, G3PCF_STAGE_ADJ_COEF, st);
+    if ((e = launch_adj_matrix(grad_zeta, w.lay, at<double>(ws, w.mht), st)) != hipSuccess)
+      return hip_fail(e, "adjoint matrices");
+  }
   PairArgs a = pair_args(p, w, ws);
   const int fp64 = (p.pair_prec == G3PCF_PREC_FP64);
   Counters* c = at<Counters>(ws, w.counters);
@@ -433,6 +440,8 @@ int g3pcf_backward(const g3pcf_problem* prob, const double* grad_zeta, double* g
     j.table = tab;
     j.gcoef = at<double>(ws, w.gcoef);
     j.grad_w = gsort;
+    j.MHt = at<double>(ws, w.mht);
+    j.H = at<double>(ws, w.hrows);
     {
       StageScope sc(p.trace, G3PCF_STAGE_ADJ_COEF, st);
       if ((e = launch_adj_coef(j, st)) != hipSuccess) return hip_fail(e, "adjoint coefficients");

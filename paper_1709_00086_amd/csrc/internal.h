@@ -153,9 +153,13 @@ struct AdjArgs {
   RowLayout lay;
   int basis;
   const ConvTable* table;    // device copy of the conversion table
+  const double* MHt;         // adjoint matrices M_H^m, transposed
+  double* H;                 // [p_count][W] H rows
   double* gcoef;             // [p_count][nbins][T]
   double* grad_w;            // [n] cell order
 };
+size_t adj_matrix_doubles(const RowLayout& L);
+hipError_t launch_adj_matrix(const double* gz, const RowLayout& L, double* MHt, hipStream_t st);
 hipError_t launch_adj_coef(const AdjArgs& a, hipStream_t st);
 hipError_t launch_unpermute(const double* gs, const int* perm, int64_t n, int accumulate,
                             double* grad, hipStream_t st);

@@ -55,8 +55,11 @@ hipError_t conv_table_device(int basis, const ConvTable** out) {
 namespace {
 
 // ---------------------------------------------------------------- per-wave LDS
-template <typename Real>
+// M holds the shell's reduced monomial sums (forward) or, in the adjoint, the
+// FP64 polynomial coefficients g_t of the shell.
+template <typename Real, bool ADJ>
 struct WaveLds {
+  using MT = std::conditional_t<ADJ, double, Real>;
   int cnt[kMaxBins];
   int cur[kMaxBins];
   int off[kMaxBins];
@@ -64,7 +67,7 @@ struct WaveLds {
   int seg_g0[kMaxSegments];
   int seg_g1[kMaxSegments];
   int seg_code[kMaxSegments];  // image shift (kx+1) + 3 (ky+1) + 9 (kz+1)
-  Real M[kTermsCart + 1];      // reduced monomial sums (+1 padding slot)
+  MT M[kTermsCart + 1];        // (+1 padding slot)
 };
 
 constexpr int kWavesPerBlock = 4;
@@ -112,9 +115,9 @@ __device__ __forceinline__ int cell_floor(double x, double lo, double inv_s) {
 // Table of candidate runs of a primary at p: one lane per (cy, cz) row of
 // cells within reach; each row contributes one or two contiguous runs of
 // galaxies (two where the x window wraps around a periodic box).
-template <typename Real>
+template <typename Lds>
 __device__ __forceinline__ void build_segments(const PairArgs& a, const int* __restrict__ cs,
-                                               const double p[3], WaveLds<Real>& W) {
+                                               const double p[3], Lds& W) {
   const int lane = threadIdx.x % kWave;
   const double R = a.rmax_search;
   int c0[3], c1[3];
@@ -273,11 +276,12 @@ struct Occ {
 template <typename Real, int BASIS, bool ADJOINT>
 struct PairKernel {
   using V = typename V4<Real>::T;
+  using Lds = WaveLds<Real, ADJOINT>;
 
   // All lanes visit every candidate of the segment table; f(j, bin) is called
   // by every lane (bin = -1 for a rejected or absent candidate).
   template <typename F>
-  static __device__ __forceinline__ void scan(const PairArgs& a, const WaveLds<Real>& W,
+  static __device__ __forceinline__ void scan(const PairArgs& a, const Lds& W,
                                               const V* __restrict__ pos4, const double p[3],
                                               PairTest<Real>& T, F&& f) {
     const int lane = threadIdx.x % kWave;
@@ -308,10 +312,10 @@ struct PairKernel {
 
   static __device__ __forceinline__ void run(const PairArgs& a) {
     extern __shared__ char smem_raw[];
-    WaveLds<Real>* lds = reinterpret_cast<WaveLds<Real>*>(smem_raw);
+    Lds* lds = reinterpret_cast<Lds*>(smem_raw);
     const int wid = threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
-    WaveLds<Real>& W = lds[wid];
+    Lds& W = lds[wid];
     const int gwave = blockIdx.x * kWavesPerBlock + wid;
     int* scratch = a.scratch + size_t(gwave) * a.scratch_per_wave;
     const V* __restrict__ pos4 = static_cast<const V*>(a.pos4);
@@ -501,7 +505,7 @@ struct PairKernel {
   // DPP, then one fold across rows leaves the four totals in rows 0..3, and
   // every lane stores its row's total (16 lanes write the same value).
   template <class Chunk>
-  static __device__ __forceinline__ void reduce_store(WaveLds<Real>& W, Chunk& ch) {
+  static __device__ __forceinline__ void reduce_store(Lds& W, Chunk& ch) {
     constexpr int NT = Chunk::NT;
     constexpr int kJunk = kTermsCart;  // slot that absorbs padding in the last group
     const int row = (threadIdx.x % kWave) >> 4;
@@ -524,7 +528,7 @@ struct PairKernel {
   }
 
   // Convert the shell's monomial sums in W.M to a_lm (FP64) and write them.
-  static __device__ __forceinline__ void convert(const PairArgs& a, const WaveLds<Real>& W,
+  static __device__ __forceinline__ void convert(const PairArgs& a, const Lds& W,
                                                  int b, long long row) {
     const int lane = threadIdx.x % kWave;
     const ConvTable& t = g_conv[BASIS];
@@ -541,17 +545,36 @@ struct PairKernel {
     }
   }
 
-  static __device__ __forceinline__ void load_gcoef(const PairArgs& a, WaveLds<Real>& W, int b,
+  static __device__ __forceinline__ void load_gcoef(const PairArgs& a, Lds& W, int b,
                                                     long long row) {
     const int lane = threadIdx.x % kWave;
     constexpr int T = (BASIS == G3PCF_BASIS_SPIN) ? kTermsSpin : kTermsCart;
     const double* g = a.gcoef + (row * a.nbins + b) * T;
-    for (int t = lane; t < T; t += kWave) W.M[t] = Real(g[t]);
+    for (int t = lane; t < T; t += kWave) W.M[t] = g[t];
     wave_lds_fence();
   }
 
+  // Adjoint scatter over a list: per pair the full polynomial
+  // sum_t g_t mono_t(u) in FP64 (its coefficients cancel strongly at l = 10),
+  // with the coefficients read from LDS through an offset the compiler cannot
+  // hoist out of the loop, so they do not occupy registers.
+  static __device__ __forceinline__ void scatter(const PairArgs& a, const Lds& W,
+                                                 const V* __restrict__ pos4, const double p[3],
+                                                 const Real* Rm, const int* list, int count,
+                                                 double w_prim) {
+    using Poly = std::conditional_t<BASIS == G3PCF_BASIS_SPIN, SpinChunk<double, 0, kDeg>,
+                                    CartChunk<double, (1u << (kDeg + 1)) - 1>>;
+    stream(a, pos4, p, Rm, list, count, [&](Real ux, Real uy, Real uz, Real, int j, bool valid) {
+      int off = 0;
+      asm volatile("" : "+v"(off));
+      const double v = Poly::poly(double(ux), double(uy), double(uz),
+                                  [&](int t) { return W.M[t + off]; });
+      if (valid) unsafeAtomicAdd(&a.grad_w[j], w_prim * v);
+    });
+  }
+
   // Forward: all chunks of one shell from a list, then conversion.
-  static __device__ __forceinline__ void shell(const PairArgs& a, WaveLds<Real>& W,
+  static __device__ __forceinline__ void shell(const PairArgs& a, Lds& W,
                                                const V* __restrict__ pos4, const double p[3],
                                                const Real* Rm, int b, const int* list,
                                                int count, long long row, double w_prim) {
@@ -571,21 +594,14 @@ struct PairKernel {
     } else {
       if (count == 0) return;
       load_gcoef(a, W, b, row);
-      for_each_chunk(CL{}, [&](auto* tag) {
-        using Chunk = std::remove_pointer_t<decltype(tag)>;
-        stream(a, pos4, p, Rm, list, count,
-               [&](Real ux, Real uy, Real uz, Real, int j, bool valid) {
-                 const Real v = Chunk::poly(ux, uy, uz, [&](int t) { return W.M[t]; });
-                 if (valid) unsafeAtomicAdd(&a.grad_w[j], w_prim * double(v));
-               });
-      });
+      scatter(a, W, pos4, p, Rm, list, count, w_prim);
       wave_lds_fence();
     }
   }
 
   // A shell with more pairs than the scratch holds: slices of S pairs in a
   // deterministic order (ballot ranks), the search repeated per slice.
-  static __device__ void process_sliced(const PairArgs& a, WaveLds<Real>& W, int* scratch,
+  static __device__ void process_sliced(const PairArgs& a, Lds& W, int* scratch,
                                         const V* __restrict__ pos4, const double p[3],
                                         PairTest<Real>& T, const Real* Rm, int b, int cb,
                                         long long row, double w_prim) {
@@ -621,14 +637,7 @@ struct PairKernel {
       load_gcoef(a, W, b, row);
       for (int s0 = 0; s0 < cb; s0 += S) {
         fill_slice(s0);
-        for_each_chunk(CL{}, [&](auto* tag) {
-          using Chunk = std::remove_pointer_t<decltype(tag)>;
-          stream(a, pos4, p, Rm, scratch, min(S, cb - s0),
-                 [&](Real ux, Real uy, Real uz, Real, int j, bool valid) {
-                   const Real v = Chunk::poly(ux, uy, uz, [&](int t) { return W.M[t]; });
-                   if (valid) unsafeAtomicAdd(&a.grad_w[j], w_prim * double(v));
-                 });
-        });
+        scatter(a, W, pos4, p, Rm, scratch, min(S, cb - s0), w_prim);
       }
       wave_lds_fence();
     }
@@ -649,7 +658,7 @@ hipError_t launch_one(const PairArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(k_zero_queue, dim3(1), dim3(1), 0, st, a.queue);
   const long long want = (a.p_count + kWavesPerBlock - 1) / kWavesPerBlock;
   const unsigned blocks = unsigned(std::min<long long>(want, kPairWaves / kWavesPerBlock));
-  const size_t lds = sizeof(WaveLds<Real>) * kWavesPerBlock;
+  const size_t lds = sizeof(typename PairKernel<Real, BASIS, ADJOINT>::Lds) * kWavesPerBlock;
   hipLaunchKernelGGL((k_pairs<Real, BASIS, ADJOINT>), dim3(blocks > 0 ? blocks : 1),
                      dim3(kWave * kWavesPerBlock), lds, st, a);
   return hipGetLastError();
