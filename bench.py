@@ -49,6 +49,24 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(basis, precision, workload):
+    """HBM bytes per pair-kernel launch from the committed FETCH_SIZE /
+    WRITE_SIZE profile, or None if the kernel sources changed since then or
+    the profile does not cover this configuration."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "pair_kernel_uniform_n1048576_traffic.json")
+    if not (os.path.exists(path) and basis == "spin" and precision != "fp64"
+            and workload == "c2"):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for f in rec["source_files"]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -182,7 +200,7 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": achieved_tflops / peak,
-            "traffic": None,
+            "traffic": measured_traffic(args.basis, args.precision, args.workload),
         },
     }
 
