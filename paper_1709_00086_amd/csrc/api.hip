@@ -101,7 +101,7 @@ Ws plan(const g3pcf_problem& p, int backward) {
   w.plist = take(size_t(n) * 4);
   w.scan = take(w.scan_bytes);
   w.counters = take(256);
-  w.scratch = take(size_t(kPairWaves) * w.S * 4);
+  w.scratch = take(size_t(kPairWaves) * 2 * w.S * 4);
   w.A = take(size_t(w.PB) * w.lay.W * 8);
   w.C = take(size_t(kZetaSplitK) * sum_wm2(w.lay) * 8);
   w.ops = (!backward && p.zeta_prec == G3PCF_PREC_BF16X3) ? take(size_t(6) * w.lay.W * w.Kp * 2)
@@ -209,6 +209,7 @@ PairArgs pair_args(const g3pcf_problem& p, const Ws& w, void* ws) {
   a.nprim = &c->nprim;
   a.scratch = at<int>(ws, w.scratch);
   a.scratch_per_wave = w.S;
+  a.packed_lists = (p.n < (int64_t(1) << 27)) ? 1 : 0;
   a.queue = &c->queue;
   a.pairs = &c->pairs;
   for (int k = 0; k < 3; ++k) {

@@ -84,7 +84,8 @@ struct PairArgs {
   const int* plist;          // [*nprim] primary slots in cell order
   const long long* nprim;    // device scalar: number of primaries
   int* scratch;              // per-wave neighbour lists
-  int scratch_per_wave;
+  int scratch_per_wave;      // list capacity S; each wave owns 2 S ints (sorted | unsorted)
+  int packed_lists;          // n < 2^27: list entries carry the shell in their top bits
   int* queue;                // device scalar: next primary (relative to p_begin)
   unsigned long long* pairs; // device scalar: accepted pairs
   long long p_begin;         // first primary of this pair-block

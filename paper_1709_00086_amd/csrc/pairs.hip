@@ -7,9 +7,13 @@
 // schedule).  For its primary the wave
 //   0. builds a table of candidate runs in LDS: one lane per (cy, cz) row of
 //      cells, all cell-start lookups in flight at once;
-//   1. counts the accepted secondaries per radial shell (search pass 1);
-//   2. writes their indices into per-shell lists in its own scratch (search
-//      pass 2) -- the GPU form of the paper's per-shell pair buckets;
+//   1. searches the runs once, counting the accepted secondaries per radial
+//      shell and appending (index, shell) to an unsorted list in its own
+//      scratch;
+//   2. sorts that list by shell (counting sort through LDS counters) into
+//      per-shell lists -- the GPU form of the paper's per-shell pair buckets.
+//      A primary with more pairs than the scratch holds instead fills groups
+//      of shells by repeated searches;
 //   3. for each shell streams its list with one pair per lane, accumulating
 //      every monomial sum in registers (vectorised over pairs, not over
 //      monomials, as in the paper's vectorisation section) with the gathers of
@@ -17,8 +21,8 @@
 //      (primary, shell) with DPP;
 //   4. converts the shell's monomial sums to a_lm in FP64 and writes them to
 //      the primary's row of A.
-// The search passes load four candidates per lane before testing any, so a
-// wave keeps four loads in flight.
+// The search loads four candidates per lane before testing any, so a wave
+// keeps four loads in flight.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -72,6 +76,7 @@ struct WaveLds {
 
 constexpr int kWavesPerBlock = 4;
 constexpr int kUnroll = 4;  // candidate loads in flight per lane
+constexpr unsigned kShellShift = 27;  // list entry = galaxy index | shell << 27 (unsigned)
 
 __device__ __forceinline__ void wave_lds_fence() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
@@ -313,11 +318,12 @@ struct PairKernel {
   static __device__ __forceinline__ void run(const PairArgs& a) {
     extern __shared__ char smem_raw[];
     Lds* lds = reinterpret_cast<Lds*>(smem_raw);
-    const int wid = threadIdx.x / kWave;
+    // wave index made uniform so that per-wave pointers live in scalar registers
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x % kWave;
     Lds& W = lds[wid];
     const int gwave = blockIdx.x * kWavesPerBlock + wid;
-    int* scratch = a.scratch + size_t(gwave) * a.scratch_per_wave;
+    int* scratch = a.scratch + size_t(gwave) * 2 * a.scratch_per_wave;
     const V* __restrict__ pos4 = static_cast<const V*>(a.pos4);
     const int* __restrict__ cs = a.cell_start;
     const long long P = min(a.p_count, (long long)(*a.nprim) - a.p_begin);
@@ -377,12 +383,21 @@ struct PairKernel {
       T.nbins = nb;
       T.rmax_d = a.rmax;
 
-      // ---- pass 0: candidate runs; pass 1: count accepted secondaries per shell
+      // ---- pass 0: candidate runs.  Pass 1: one search that counts the
+      // accepted secondaries per shell and appends (index | shell << 27) to an
+      // unsorted list in the second half of the scratch.
       build_segments(a, cs, p, W);
       if (lane < nb) W.cnt[lane] = 0;
       wave_lds_fence();
-      scan(a, W, pos4, p, T, [&](int, int b) {
-        if (b >= 0) atomicAdd(&W.cnt[b], 1);
+      unsigned* unsorted = reinterpret_cast<unsigned*>(scratch + S);
+      int appended = 0;
+      scan(a, W, pos4, p, T, [&](int j, int b) {
+        const bool hit = b >= 0;
+        if (hit) atomicAdd(&W.cnt[b], 1);
+        const unsigned long long m = __ballot(hit);
+        const int at = appended + lanes_below(m);
+        if (hit && at < S && a.packed_lists) unsorted[at] = unsigned(j) | (unsigned(b) << kShellShift);
+        appended += __popcll(m);
       });
       wave_lds_fence();
 
@@ -394,7 +409,49 @@ struct PairKernel {
       double w_prim = 0.0;
       if constexpr (ADJOINT) w_prim = a.wsort[slot];
 
-      // ---- passes 2 and 3 over groups of shells that fit in the scratch
+      if (total <= S && a.packed_lists) {
+        // ---- pass 2: counting sort of the unsorted list by shell
+        if (lane == 0) {
+          int off = 0;
+          for (int b = 0; b < nb; ++b) {
+            W.off[b] = off;
+            W.cur[b] = 0;
+            off += W.cnt[b];
+          }
+        }
+        wave_lds_fence();
+        // eight entries per lane in flight: loads, then the LDS slot atomics,
+        // then the stores
+        constexpr int kSortUnroll = 8;
+        for (int base = 0; base < total; base += kSortUnroll * kWave) {
+          unsigned e[kSortUnroll];
+          int at[kSortUnroll];
+#pragma unroll
+          for (int u = 0; u < kSortUnroll; ++u)
+            e[u] = unsorted[min(base + u * kWave + lane, total - 1)];
+#pragma unroll
+          for (int u = 0; u < kSortUnroll; ++u) {
+            const bool ok = base + u * kWave + lane < total;
+            at[u] = ok ? atomicAdd(&W.cur[e[u] >> kShellShift], 1) : 0;
+          }
+#pragma unroll
+          for (int u = 0; u < kSortUnroll; ++u) {
+            if (base + u * kWave + lane < total)
+              scratch[W.off[e[u] >> kShellShift] + at[u]] = int(e[u] & ((1u << kShellShift) - 1u));
+          }
+        }
+        wave_lds_fence();
+        // ---- pass 3: every shell from its list
+        for (int b = 0; b < nb; ++b) {
+          const int cb = uniform_int(W.cnt[b]);
+          const int* list = scratch + uniform_int(W.off[b]);
+          shell(a, W, pos4, p, Rm, b, list, cb, row, w_prim);
+        }
+        continue;
+      }
+
+      // ---- more pairs than the scratch holds: groups of shells that fit,
+      // each filled by a repeated search
       int b = 0;
       while (b < nb) {
         const int cb = uniform_int(W.cnt[b]);

@@ -84,12 +84,17 @@ _CATS = {
                             periodic=True, los="z"),
     "small_open_f32": _tiny(n=2000, L=200.0, seed=16, rmax=60.0, nbins=10, lmax=10,
                             periodic=False, los="z", dtype=np.float32, box_lo=(-50.0, 10.0, 3.0)),
+    # the maximum number of shells (list entries carry shells >= 16 in their
+    # top bits); float32 positions whose separations all keep >= 9e-5 from a
+    # shell edge and from R_max, so FP32 binning agrees with FP64 binning
+    "small_32_shells": _tiny(n=600, L=200.0, seed=19, rmax=60.0, nbins=32, lmax=10,
+                             periodic=True, los="z", dtype=np.float32),
     "config1": lambda: (C.config1(), None),
     "config1_weighted": lambda: (C.config1_weighted(), None),
 }
 
 SMALL = ["tiny_periodic_tight", "tiny_open", "tiny_observer_open", "tiny_observer_periodic",
-         "small_periodic", "small_open_f32"]
+         "small_periodic", "small_open_f32", "small_32_shells"]
 
 
 @pytest.mark.parametrize("basis", ["cartesian", "spin"])
