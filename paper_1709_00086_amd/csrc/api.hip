@@ -61,11 +61,10 @@ size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Ws {
   size_t pos4, tmp4, cid, perm, tmp_perm, wsort, cell_start, cell_count, flags, plist, scan,
-      counters, scratch, A, C, ops, gcoef, gsort, mht, hrows;
+      counters, A, C, ops, gcoef, gsort, mht, hrows;
   size_t scan_bytes;
   size_t total;
   int64_t PB;   // primaries per pair-block
-  int S;        // scratch entries per wave
   int Kp;       // padded rows of a zeta sub-block (bf16 operands)
   Grid grid;
   RowLayout lay;
@@ -80,7 +79,6 @@ Ws plan(const g3pcf_problem& p, int backward) {
   w.lay = make_layout(p.lmax, p.nbins);
   const int64_t ncell = w.grid.ncell;
   w.PB = std::max<int64_t>(1, std::min<int64_t>(n, kPairBlockMax));
-  w.S = int(std::min<int64_t>(kScratchMax, std::max<int64_t>(64, (n + 63) / 64 * 64)));
   w.Kp = ((std::min<int64_t>(kZetaBlock, w.PB) + 31) / 32) * 32;
   w.scan_bytes = scan_tmp_bytes(std::max<int64_t>(ncell + 1, n + 1));
   size_t at = 0;
@@ -101,7 +99,6 @@ Ws plan(const g3pcf_problem& p, int backward) {
   w.plist = take(size_t(n) * 4);
   w.scan = take(w.scan_bytes);
   w.counters = take(256);
-  w.scratch = take(size_t(kPairWaves) * 2 * w.S * 4);
   w.A = take(size_t(w.PB) * w.lay.W * 8);
   w.C = take(size_t(kZetaSplitK) * sum_wm2(w.lay) * 8);
   w.ops = (!backward && p.zeta_prec == G3PCF_PREC_BF16X3) ? take(size_t(6) * w.lay.W * w.Kp * 2)
@@ -207,9 +204,6 @@ PairArgs pair_args(const g3pcf_problem& p, const Ws& w, void* ws) {
   a.cell_start = at<int>(ws, w.cell_start);
   a.plist = at<int>(ws, w.plist);
   a.nprim = &c->nprim;
-  a.scratch = at<int>(ws, w.scratch);
-  a.scratch_per_wave = w.S;
-  a.packed_lists = (p.n < (int64_t(1) << 27)) ? 1 : 0;
   a.queue = &c->queue;
   a.pairs = &c->pairs;
   for (int k = 0; k < 3; ++k) {
@@ -224,6 +218,14 @@ PairArgs pair_args(const g3pcf_problem& p, const Ws& w, void* ws) {
   a.periodic = w.grid.periodic;
   a.rmax = p.rmax;
   a.rmax_search = w.grid.rsearch;
+  // squared shell edges rounded to float; the lower bound is exclusive, so it
+  // is the float just below the edge (0 for the innermost shell, r > 0)
+  for (int b = 0; b < p.nbins; ++b) {
+    const double e0 = b * p.rmax / p.nbins, e1 = (b + 1) * p.rmax / p.nbins;
+    const float t0 = float(e0 * e0);
+    a.r2_lo[b] = (b == 0) ? 0.0f : std::nextafter(t0, 0.0f);
+    a.r2_hi[b] = (b + 1 == p.nbins) ? float(p.rmax * p.rmax) : float(e1 * e1);
+  }
   a.nbins = p.nbins;
   a.lmax = p.lmax;
   a.los = p.los;

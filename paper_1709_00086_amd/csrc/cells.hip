@@ -245,29 +245,21 @@ Grid make_grid(const g3pcf_problem& p) {
   for (int a = 0; a < 3; ++a)
     ext = std::max(ext, std::fabs(p.box_lo[a]) + std::fabs(p.box[a]));
   g.rsearch = p.rmax * (1.0 + 1e-5) + 1e-6 * ext + 1e-9;
-  // Cells of about R_max / 4: a row (cy, cz) of cells is a contiguous run of
-  // galaxies, and the search window spans about nine cells per axis.
-  const double target = p.rmax / 4.0;
+  // Cells of about R_max / 8 across the rows and R_max / 16 along x: a row
+  // (cy, cz) of cells is a contiguous run of galaxies, and the x-interval of
+  // an annulus in a row is cut to within one thin cell at each end.
+  const double target[3] = {p.rmax / 16.0, p.rmax / 8.0, p.rmax / 8.0};
   int64_t cap = std::max<int64_t>(64, 4 * p.n);
   cap = std::min<int64_t>(cap, int64_t(1) << 24);
   for (int a = 0; a < 3; ++a) {
     g.lo[a] = p.box_lo[a];
     g.L[a] = p.box[a];
-    double nc = std::floor(p.box[a] / target);
-    nc = std::max(1.0, std::min(nc, 1024.0));
+    double nc = std::floor(p.box[a] / target[a]);
+    nc = std::max(1.0, std::min(nc, 4096.0));
     g.nc[a] = int(nc);
   }
   while (int64_t(g.nc[0]) * g.nc[1] * g.nc[2] > cap) {
     for (int a = 0; a < 3; ++a) g.nc[a] = std::max(1, (g.nc[a] * 4) / 5);
-  }
-  // A search window must span at most kMaxRows (cy, cz) rows of cells.
-  auto window = [&](int a) {
-    const double s = g.L[a] / g.nc[a];
-    const int w = int(std::floor(2.0 * g.rsearch / s)) + 2;
-    return std::min(w, g.nc[a]);
-  };
-  while (window(1) * window(2) > kMaxRows) {
-    for (int a = 1; a < 3; ++a) g.nc[a] = std::max(1, std::min(g.nc[a] - 1, (g.nc[a] * 9) / 10));
   }
   for (int a = 0; a < 3; ++a) {
     g.s[a] = g.L[a] / g.nc[a];

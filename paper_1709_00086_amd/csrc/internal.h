@@ -28,12 +28,6 @@ constexpr int kZetaSplitK = 4;
 constexpr int kPairWaves = 4096;
 // Maximum pair-block (primaries whose a_lm rows are held at once).
 constexpr int kPairBlockMax = 131072;
-// Per-wave scratch (neighbour indices) upper bound.
-constexpr int kScratchMax = 1 << 16;
-// Candidate runs per primary held in LDS: at most two per (cy, cz) row of
-// cells, and the grid is chosen so that a search window spans <= 128 rows.
-constexpr int kMaxSegments = 256;
-constexpr int kMaxRows = kMaxSegments / 2;
 
 // Sparse monomial -> a_lm conversion table, one row per real output of a
 // shell.  Output o = (m, part, l) with part 0 = Re, 1 = Im (m >= 1 only).
@@ -83,9 +77,6 @@ struct PairArgs {
   const int* cell_start;     // [ncell + 1]
   const int* plist;          // [*nprim] primary slots in cell order
   const long long* nprim;    // device scalar: number of primaries
-  int* scratch;              // per-wave neighbour lists
-  int scratch_per_wave;      // list capacity S; each wave owns 2 S ints (sorted | unsorted)
-  int packed_lists;          // n < 2^27: list entries carry the shell in their top bits
   int* queue;                // device scalar: next primary (relative to p_begin)
   unsigned long long* pairs; // device scalar: accepted pairs
   long long p_begin;         // first primary of this pair-block
@@ -96,6 +87,9 @@ struct PairArgs {
   int periodic;
   int tight[3];
   double rmax, rmax_search;
+  // FP32 shell test: shell b holds r^2 with r2_lo[b] < r^2 < r2_hi[b] (floats
+  // next to the squared shell edges, so the shells partition the floats)
+  float r2_lo[kMaxBins], r2_hi[kMaxBins];
   int nbins;
   int lmax;
   int los;                   // 0 z, 1 observer

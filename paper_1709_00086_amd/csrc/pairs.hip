@@ -4,28 +4,34 @@
 //
 // One wavefront owns one primary at a time and pulls primaries from a shared
 // counter (dynamic scheduling over primaries, as the paper's OpenMP dynamic
-// schedule).  For its primary the wave
-//   0. builds a table of candidate runs in LDS: one lane per (cy, cz) row of
-//      cells, all cell-start lookups in flight at once;
-//   1. searches the runs once, counting the accepted secondaries per radial
-//      shell and appending (index, shell) to an unsorted list in its own
-//      scratch;
-//   2. sorts that list by shell (counting sort through LDS counters) into
-//      per-shell lists -- the GPU form of the paper's per-shell pair buckets.
-//      A primary with more pairs than the scratch holds instead fills groups
-//      of shells by repeated searches;
-//   3. for each shell streams its list with one pair per lane, accumulating
-//      every monomial sum in registers (vectorised over pairs, not over
-//      monomials, as in the paper's vectorisation section) with the gathers of
-//      the next pairs in flight, then reduces the per-lane partials once per
-//      (primary, shell) with DPP;
-//   4. converts the shell's monomial sums to a_lm in FP64 and writes them to
-//      the primary's row of A.
-// The search loads four candidates per lane before testing any, so a wave
-// keeps four loads in flight.
+// schedule).  For its primary the wave takes the radial shells one after the
+// other; for shell b it
+//   1. builds, 64 rows of cells at a time (one lane per (cy, cz) row), the
+//      runs of galaxies that can lie in the annulus: per row the x-interval
+//      of the outer sphere minus the x-interval of the inner sphere, i.e. at
+//      most two contiguous ranges of cells (four where they wrap around a
+//      periodic box).  All cell-start lookups of the 64 rows are in flight at
+//      once, and the runs go into a table in LDS with their prefix sums;
+//   2. streams the runs' galaxies with one candidate per lane (a lane finds
+//      its run from the prefix sums), bins each candidate, and appends the
+//      accepted ones, already rotated and normalised, to a ring of pairs in
+//      LDS -- the GPU form of the paper's per-bin pair buckets;
+//   3. whenever the ring holds a full wave of pairs, accumulates them, one
+//      pair per lane, into every monomial sum of the shell held in registers
+//      (vectorised over pairs, not over monomials, as in the paper's
+//      vectorisation section);
+//   4. reduces the per-lane partials once per (primary, shell) with DPP and
+//      converts the shell's monomial sums to a_lm in FP64.
+// No neighbour list ever leaves the compute unit.  A basis whose sums do not
+// fit in registers at once is accumulated in chunks, each with its own
+// search of the shell.
+//
+// The adjoint kernel runs the same search and, per accepted pair, evaluates
+// the shell's adjoint polynomial and adds it to the secondary's gradient.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <type_traits>
 #include <utility>
@@ -58,25 +64,36 @@ hipError_t conv_table_device(int basis, const ConvTable** out) {
 
 namespace {
 
+constexpr int kWavesPerBlock = 4;
+constexpr int kMaxRuns = 4 * kWave;  // runs of one chunk of 64 rows (<= 4 per row)
+constexpr int kRing = 2 * kWave;     // accepted pairs waiting for a full wave
+
+// A run of the table.  FP32 keeps the primary's position minus the run's
+// periodic image shift (the reference the candidates are measured from).
+template <typename Real>
+struct RunEntry;
+template <>
+struct RunEntry<float> {
+  float rx, ry, rz;
+  int g0;
+};
+template <>
+struct RunEntry<double> {
+  int g0;
+};
+
 // ---------------------------------------------------------------- per-wave LDS
 // M holds the shell's reduced monomial sums (forward) or, in the adjoint, the
 // FP64 polynomial coefficients g_t of the shell.
 template <typename Real, bool ADJ>
 struct WaveLds {
+  using V = typename V4<Real>::T;
   using MT = std::conditional_t<ADJ, double, Real>;
-  int cnt[kMaxBins];
-  int cur[kMaxBins];
-  int off[kMaxBins];
-  int nseg;
-  int seg_g0[kMaxSegments];
-  int seg_g1[kMaxSegments];
-  int seg_code[kMaxSegments];  // image shift (kx+1) + 3 (ky+1) + 9 (kz+1)
+  int pre[kMaxRuns];           // first virtual candidate index of each run
+  RunEntry<Real> run[kMaxRuns];
+  V ring[kRing];               // (u_x, u_y, u_z, w) forward; (u_x, u_y, u_z, index) adjoint
   MT M[kTermsCart + 1];        // (+1 padding slot)
 };
-
-constexpr int kWavesPerBlock = 4;
-constexpr int kUnroll = 4;  // candidate loads in flight per lane
-constexpr unsigned kShellShift = 27;  // list entry = galaxy index | shell << 27 (unsigned)
 
 __device__ __forceinline__ void wave_lds_fence() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
@@ -87,24 +104,47 @@ __device__ __forceinline__ int lanes_below(unsigned long long m) {
   return __builtin_amdgcn_mbcnt_hi(unsigned(m >> 32), __builtin_amdgcn_mbcnt_lo(unsigned(m), 0));
 }
 
-// ---------------------------------------------------------------- candidate search
-__device__ __forceinline__ double axis_box_dist(double p, int c_u, int nc, double lo, double s,
-                                                int periodic, int tight, double L) {
-  if (tight) {  // min over the images of wrapped cell c_u
+__device__ __forceinline__ int wave_incl_scan(int x) {
+  const int lane = threadIdx.x % kWave;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int y = __shfl_up(x, off);
+    if (lane >= off) x += y;
+  }
+  return x;
+}
+
+// index <-> last component of a ring entry
+__device__ __forceinline__ float pack_index(int j, float) { return __int_as_float(j); }
+__device__ __forceinline__ double pack_index(int j, double) { return double(j); }
+__device__ __forceinline__ int unpack_index(float v) { return __float_as_int(v); }
+__device__ __forceinline__ int unpack_index(double v) { return int(v); }
+
+// ---------------------------------------------------------------- geometry
+// Distance range along one axis from p to cell c_u (unwrapped index): the
+// nearest and farthest points of the cell.  The outer cells of an open box
+// also hold any point beyond it, and on a tight periodic axis the nearest
+// distance is taken over the images (the farthest is then not used).
+__device__ __forceinline__ void axis_range(double p, int c_u, int nc, double lo, double s,
+                                           int periodic, int tight, double L, double& dmin,
+                                           double& dmax) {
+  if (tight) {
     double best = 1e300;
     for (int k = -1; k <= 1; ++k) {
       const double a = lo + c_u * s + k * L, b = a + s;
-      const double d = fmax(0.0, fmax(a - p, p - b));
-      best = fmin(best, d);
+      best = fmin(best, fmax(0.0, fmax(a - p, p - b)));
     }
-    return best;
+    dmin = best;
+    dmax = 1e300;
+    return;
   }
   double a = lo + c_u * s, b = a + s;
-  if (!periodic) {  // the outer cells also hold any point beyond the box
+  if (!periodic) {
     if (c_u == 0) a = -1e300;
     if (c_u == nc - 1) b = 1e300;
   }
-  return fmax(0.0, fmax(a - p, p - b));
+  dmin = fmax(0.0, fmax(a - p, p - b));
+  dmax = fmax(fabs(a - p), fabs(b - p));
 }
 
 __device__ __forceinline__ int floor_div(int a, int b) {
@@ -114,160 +154,41 @@ __device__ __forceinline__ int floor_div(int a, int b) {
 }
 
 __device__ __forceinline__ int cell_floor(double x, double lo, double inv_s) {
-  return int(floor((x - lo) * inv_s));
+  // clamp before the conversion so that far-away coordinates cannot overflow
+  const double c = floor((x - lo) * inv_s);
+  return int(fmin(fmax(c, -1e9), 1e9));
 }
 
-// Table of candidate runs of a primary at p: one lane per (cy, cz) row of
-// cells within reach; each row contributes one or two contiguous runs of
-// galaxies (two where the x window wraps around a periodic box).
-template <typename Lds>
-__device__ __forceinline__ void build_segments(const PairArgs& a, const int* __restrict__ cs,
-                                               const double p[3], Lds& W) {
-  const int lane = threadIdx.x % kWave;
-  const double R = a.rmax_search;
-  int c0[3], c1[3];
-  for (int ax = 1; ax < 3; ++ax) {
-    if (a.tight[ax]) {
-      c0[ax] = 0;
-      c1[ax] = a.nc[ax] - 1;
-    } else {
-      c0[ax] = cell_floor(p[ax] - R, a.lo[ax], a.inv_s[ax]);
-      c1[ax] = cell_floor(p[ax] + R, a.lo[ax], a.inv_s[ax]);
-      if (!a.periodic) {
-        c0[ax] = min(max(c0[ax], 0), a.nc[ax] - 1);
-        c1[ax] = min(max(c1[ax], 0), a.nc[ax] - 1);
-      }
-    }
-  }
-  const int nx = a.nc[0], ny = a.nc[1], nz = a.nc[2];
-  const int nyr = c1[1] - c0[1] + 1, nzr = c1[2] - c0[2] + 1;
-  const int nrows = nyr * nzr;
-  int nseg = 0;
-  for (int rb = 0; rb < nrows; rb += kWave) {
-    const int r = rb + lane;
-    int n_here = 0;
-    int g0a = 0, g1a = 0, ca = 0, g0b = 0, g1b = 0, cb = 0;
-    if (r < nrows) {
-      const int czu = c0[2] + r / nyr, cyu = c0[1] + r % nyr;
-      const double dz =
-          axis_box_dist(p[2], czu, nz, a.lo[2], a.s[2], a.periodic, a.tight[2], a.L[2]);
-      const double dy =
-          axis_box_dist(p[1], cyu, ny, a.lo[1], a.s[1], a.periodic, a.tight[1], a.L[1]);
-      const double d2 = dy * dy + dz * dz;
-      if (d2 < R * R) {
-        int cz = czu, cy = cyu, kz = 0, ky = 0;
-        if (a.periodic && !a.tight[2]) {
-          kz = floor_div(czu, nz);
-          cz = czu - kz * nz;
-        }
-        if (a.periodic && !a.tight[1]) {
-          ky = floor_div(cyu, ny);
-          cy = cyu - ky * ny;
-        }
-        const int row = (cz * ny + cy) * nx;
-        const int cyz = 3 * (ky + 1) + 9 * (kz + 1);
-        if (a.tight[0]) {
-          g0a = cs[row];
-          g1a = cs[row + nx];
-          ca = 1 + cyz;
-          n_here = 1;
-        } else {
-          const double hx = sqrt(R * R - d2);
-          int x0 = cell_floor(p[0] - hx, a.lo[0], a.inv_s[0]);
-          int x1 = cell_floor(p[0] + hx, a.lo[0], a.inv_s[0]);
-          if (!a.periodic) {
-            x0 = min(max(x0, 0), nx - 1);
-            x1 = min(max(x1, 0), nx - 1);
-            g0a = cs[row + x0];
-            g1a = cs[row + x1 + 1];
-            ca = 1 + cyz;
-            n_here = 1;
-          } else {
-            const int k0 = floor_div(x0, nx);
-            const int a0 = x0 - k0 * nx, b0 = x1 - k0 * nx;
-            if (b0 < nx) {
-              g0a = cs[row + a0];
-              g1a = cs[row + b0 + 1];
-              ca = (k0 + 1) + cyz;
-              n_here = 1;
-            } else {
-              g0a = cs[row + a0];
-              g1a = cs[row + nx];
-              ca = (k0 + 1) + cyz;
-              g0b = cs[row];
-              g1b = cs[row + (b0 - nx) + 1];
-              cb = (k0 + 2) + cyz;
-              n_here = 2;
-            }
-          }
-        }
-      }
-    }
-    const unsigned long long m1 = __ballot(n_here >= 1), m2 = __ballot(n_here >= 2);
-    const int at = nseg + lanes_below(m1) + lanes_below(m2);
-    if (n_here >= 1 && at < kMaxSegments) {
-      W.seg_g0[at] = g0a;
-      W.seg_g1[at] = g1a;
-      W.seg_code[at] = ca;
-    }
-    if (n_here >= 2 && at + 1 < kMaxSegments) {
-      W.seg_g0[at + 1] = g0b;
-      W.seg_g1[at + 1] = g1b;
-      W.seg_code[at + 1] = cb;
-    }
-    nseg += __popcll(m1) + __popcll(m2);
-  }
-  if (lane == 0) W.nseg = min(nseg, kMaxSegments);
-  wave_lds_fence();
-}
-
-// Separation, acceptance and shell of one candidate (identical in both passes).
-template <typename Real>
-struct PairTest {
-  Real ref[3];   // primary position minus the run's image shift
-  Real L[3], invL[3];
-  bool minimg;   // recompute the minimum image per candidate
-  Real r2max;
-  Real nb_over_r;
+// ---------------------------------------------------------------- binning
+// FP64 shell of a candidate: the same operations, in the same order and
+// without contraction, as the plain definition (minimum image by
+// nearbyint(d / L), r = sqrt(r^2), shell = floor(r * nbins / R_max)).
+// Returns -1 for a rejected candidate.
+struct Bin64 {
+  double L[3];
+  bool minimg;
+  double r2max;
   int nbins;
-  double rmax_d;
+  double rmax;
 
-  __device__ __forceinline__ int bin_of(const typename V4<Real>::T& q) const;
+  __device__ __forceinline__ int classify(const double4& q, const double ref[3], double d[3],
+                                          double& r2) const {
+    d[0] = __dsub_rn(q.x, ref[0]);
+    d[1] = __dsub_rn(q.y, ref[1]);
+    d[2] = __dsub_rn(q.z, ref[2]);
+    if (minimg) {
+      // L * k is exact for k in {-1, 0, 1}, so one rounding as in the definition
+      for (int c = 0; c < 3; ++c)
+        d[c] = __dsub_rn(d[c], __dmul_rn(L[c], rint(__ddiv_rn(d[c], L[c]))));
+    }
+    r2 = __dadd_rn(__dadd_rn(__dmul_rn(d[0], d[0]), __dmul_rn(d[1], d[1])),
+                   __dmul_rn(d[2], d[2]));
+    if (!(r2 > 0.0) || !(r2 < r2max)) return -1;
+    const double r = sqrt(r2);
+    const int b = int(floor(__ddiv_rn(__dmul_rn(r, double(nbins)), rmax)));
+    return b < nbins ? b : nbins - 1;
+  }
 };
-
-template <>
-__device__ __forceinline__ int PairTest<float>::bin_of(const float4& q) const {
-  // explicit rounding everywhere: both search passes must bin identically
-  float dx = __fsub_rn(q.x, ref[0]), dy = __fsub_rn(q.y, ref[1]), dz = __fsub_rn(q.z, ref[2]);
-  if (minimg) {
-    dx = fma_r(-L[0], __builtin_rintf(__fmul_rn(dx, invL[0])), dx);
-    dy = fma_r(-L[1], __builtin_rintf(__fmul_rn(dy, invL[1])), dy);
-    dz = fma_r(-L[2], __builtin_rintf(__fmul_rn(dz, invL[2])), dz);
-  }
-  const float r2 = fma_r(dz, dz, fma_r(dy, dy, __fmul_rn(dx, dx)));
-  if (!(r2 > 0.0f) || !(r2 < r2max)) return -1;
-  const int b = int(__fmul_rn(__builtin_amdgcn_sqrtf(r2), nb_over_r));
-  return b < nbins ? b : nbins - 1;
-}
-
-// FP64: the same operations, in the same order and without contraction, as
-// the plain definition (minimum image by nearbyint(d / L), r = sqrt(r^2),
-// shell = floor(r * nbins / R_max)).
-template <>
-__device__ __forceinline__ int PairTest<double>::bin_of(const double4& q) const {
-  double d[3] = {__dsub_rn(q.x, ref[0]), __dsub_rn(q.y, ref[1]), __dsub_rn(q.z, ref[2])};
-  if (minimg) {
-    // L * k is exact for k in {-1, 0, 1}, so one rounding as in the definition
-    for (int c = 0; c < 3; ++c)
-      d[c] = __dsub_rn(d[c], __dmul_rn(L[c], rint(__ddiv_rn(d[c], L[c]))));
-  }
-  const double r2 = __dadd_rn(__dadd_rn(__dmul_rn(d[0], d[0]), __dmul_rn(d[1], d[1])),
-                              __dmul_rn(d[2], d[2]));
-  if (!(r2 > 0.0) || !(r2 < r2max)) return -1;
-  const double r = sqrt(r2);
-  const int b = int(floor(__ddiv_rn(__dmul_rn(r, double(nbins)), rmax_d)));
-  return b < nbins ? b : nbins - 1;
-}
 
 // Occupancy target per kernel (waves per SIMD); the register budget is
 // 512 / target per lane, so every accumulator chunk must fit.
@@ -277,42 +198,373 @@ struct Occ {
       ADJOINT ? 3 : ((std::is_same<Real, float>::value && BASIS == G3PCF_BASIS_SPIN) ? 3 : 2);
 };
 
+template <bool B>
+using bool_c = std::integral_constant<bool, B>;
+
 // ---------------------------------------------------------------- the kernel
 template <typename Real, int BASIS, bool ADJOINT>
 struct PairKernel {
   using V = typename V4<Real>::T;
   using Lds = WaveLds<Real, ADJOINT>;
+  static constexpr bool kF32 = std::is_same<Real, float>::value;
 
-  // All lanes visit every candidate of the segment table; f(j, bin) is called
-  // by every lane (bin = -1 for a rejected or absent candidate).
-  template <typename F>
-  static __device__ __forceinline__ void scan(const PairArgs& a, const Lds& W,
-                                              const V* __restrict__ pos4, const double p[3],
-                                              PairTest<Real>& T, F&& f) {
+  // Per-primary state shared by the shell searches.
+  struct Primary {
+    double p[3];
+    Real pref[3];  // primary position in the working precision
+    Real L[3], invL[3];
+    Real Rm[9];    // line-of-sight rotation
+    bool rotate;
+    bool minimg;   // minimum image per candidate (else the run's image shift)
+    Bin64 bin64;
+  };
+
+  // Runs of the rows [rb, rb + 64) of the window for the annulus
+  // r0 <= r < r1 into the LDS table; returns the number of runs and sets
+  // `total` to their summed length.
+  static __device__ __forceinline__ int build_runs(const PairArgs& a, const int* __restrict__ cs,
+                                                   const Primary& P, double r0, double r1,
+                                                   const int c0[3], int nyr, int rb, int nrows,
+                                                   Lds& W, int& total) {
     const int lane = threadIdx.x % kWave;
-    const int nseg = uniform_int(W.nseg);
-    for (int s = 0; s < nseg; ++s) {
-      const int g0 = uniform_int(W.seg_g0[s]), g1 = uniform_int(W.seg_g1[s]);
-      if (g1 <= g0) continue;
-      if (!T.minimg) {
-        const int code = uniform_int(W.seg_code[s]);
-        const int kx = code % 3 - 1, ky = (code / 3) % 3 - 1, kz = code / 9 - 1;
-        T.ref[0] = Real(p[0] - kx * a.L[0]);
-        T.ref[1] = Real(p[1] - ky * a.L[1]);
-        T.ref[2] = Real(p[2] - kz * a.L[2]);
-      }
-      for (int base = g0; base < g1; base += kUnroll * kWave) {
-        V q[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) q[u] = pos4[min(base + u * kWave + lane, g1 - 1)];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          const int j = base + u * kWave + lane;
-          const int b = (j < g1) ? T.bin_of(q[u]) : -1;
-          f(j, b);
+    const double* p = P.p;
+    const int nx = a.nc[0], ny = a.nc[1], nz = a.nc[2];
+    int n_here = 0;
+    int g0v[4] = {0, 0, 0, 0}, lenv[4] = {0, 0, 0, 0}, kxv[4] = {0, 0, 0, 0};
+    int ky = 0, kz = 0;
+    const int r = rb + lane;
+    if (r < nrows) {
+      const int czu = c0[2] + r / nyr, cyu = c0[1] + r % nyr;
+      double dzmin, dzmax, dymin, dymax;
+      axis_range(p[2], czu, nz, a.lo[2], a.s[2], a.periodic, a.tight[2], a.L[2], dzmin, dzmax);
+      axis_range(p[1], cyu, ny, a.lo[1], a.s[1], a.periodic, a.tight[1], a.L[1], dymin, dymax);
+      const double d2min = dymin * dymin + dzmin * dzmin;
+      if (d2min < r1 * r1) {
+        int cz = czu, cy = cyu;
+        if (a.periodic && !a.tight[2]) {
+          kz = floor_div(czu, nz);
+          cz = czu - kz * nz;
+        }
+        if (a.periodic && !a.tight[1]) {
+          ky = floor_div(cyu, ny);
+          cy = cyu - ky * ny;
+        }
+        const int row = (cz * ny + cy) * nx;
+        // up to two x-intervals of cells (unwrapped indices)
+        int ia[2] = {0, 0}, ib[2] = {0, 0}, ni = 0;
+        if (a.tight[0]) {
+          ia[0] = 0;
+          ib[0] = nx - 1;
+          ni = 1;
+        } else {
+          const double hx1 = sqrt(r1 * r1 - d2min);
+          const double d2max = dymax * dymax + dzmax * dzmax;
+          const bool cut = r0 > 0.0 && !a.tight[1] && !a.tight[2] && r0 * r0 > d2max;
+          const double hx0 = cut ? sqrt(r0 * r0 - d2max) : 0.0;
+          int a1 = cell_floor(p[0] - hx1, a.lo[0], a.inv_s[0]);
+          int b1 = cell_floor(p[0] - hx0, a.lo[0], a.inv_s[0]);
+          int a2 = cell_floor(p[0] + hx0, a.lo[0], a.inv_s[0]);
+          int b2 = cell_floor(p[0] + hx1, a.lo[0], a.inv_s[0]);
+          if (!a.periodic) {
+            a1 = min(max(a1, 0), nx - 1);
+            b1 = min(max(b1, 0), nx - 1);
+            a2 = min(max(a2, 0), nx - 1);
+            b2 = min(max(b2, 0), nx - 1);
+          }
+          if (a2 <= b1 + 1) {
+            ia[0] = a1;
+            ib[0] = b2;
+            ni = 1;
+          } else {
+            ia[0] = a1;
+            ib[0] = b1;
+            ia[1] = a2;
+            ib[1] = b2;
+            ni = 2;
+          }
+        }
+        // cell ranges -> galaxy runs (a periodic interval may wrap once)
+        int ca[4] = {0, 0, 0, 0}, cb[4] = {0, 0, 0, 0}, kk[4] = {0, 0, 0, 0}, nr = 0;
+        for (int i = 0; i < ni; ++i) {
+          if (a.periodic && !a.tight[0]) {
+            const int k0 = floor_div(ia[i], nx);
+            const int lo_c = ia[i] - k0 * nx, hi_c = ib[i] - k0 * nx;
+            if (hi_c < nx) {
+              ca[nr] = lo_c;
+              cb[nr] = hi_c;
+              kk[nr++] = k0;
+            } else {
+              ca[nr] = lo_c;
+              cb[nr] = nx - 1;
+              kk[nr++] = k0;
+              ca[nr] = 0;
+              cb[nr] = hi_c - nx;
+              kk[nr++] = k0 + 1;
+            }
+          } else {
+            ca[nr] = ia[i];
+            cb[nr] = ib[i];
+            kk[nr++] = 0;
+          }
+        }
+        int g0s[4], g1s[4];
+        for (int i = 0; i < nr; ++i) {
+          g0s[i] = cs[row + ca[i]];
+          g1s[i] = cs[row + cb[i] + 1];
+        }
+        for (int i = 0; i < nr; ++i) {
+          if (g1s[i] > g0s[i]) {
+            g0v[n_here] = g0s[i];
+            lenv[n_here] = g1s[i] - g0s[i];
+            kxv[n_here] = kk[i];
+            ++n_here;
+          }
         }
       }
     }
+    // table slots: a lane's runs follow those of the lower lanes
+    const unsigned long long m1 = __ballot(n_here >= 1), m2 = __ballot(n_here >= 2),
+                             m3 = __ballot(n_here >= 3), m4 = __ballot(n_here >= 4);
+    const int at = lanes_below(m1) + lanes_below(m2) + lanes_below(m3) + lanes_below(m4);
+    const int tot = lenv[0] + lenv[1] + lenv[2] + lenv[3];
+    const int incl = wave_incl_scan(tot);
+    int v = incl - tot;
+    for (int i = 0; i < 4; ++i) {
+      if (i < n_here) {
+        W.pre[at + i] = v;
+        RunEntry<Real> e;
+        e.g0 = g0v[i];
+        if constexpr (kF32) {
+          e.rx = float(p[0] - kxv[i] * a.L[0]);
+          e.ry = float(p[1] - ky * a.L[1]);
+          e.rz = float(p[2] - kz * a.L[2]);
+        }
+        W.run[at + i] = e;
+        v += lenv[i];
+      }
+    }
+    total = uniform_int(__shfl(incl, kWave - 1));
+    const int nrun = __popcll(m1) + __popcll(m2) + __popcll(m3) + __popcll(m4);
+    wave_lds_fence();
+    return nrun;
+  }
+
+  // Candidate of each lane in the window [v0, v0 + 64) of the chunk's runs
+  // (lanes past the end repeat the last candidate).  kb is the run holding v0
+  // on entry and the run holding v0 + 63 on return.
+  static __device__ __forceinline__ int map_window(const Lds& W, int nrun, int total, int v0,
+                                                   int& kb, Real ref[3]) {
+    const int lane = threadIdx.x % kWave;
+    const int vc = min(v0 + lane, total - 1);
+    const int kk = kb + lane;
+    const int prel = kk < nrun ? W.pre[kk] : INT_MAX;
+    // runs kb .. kb + c - 1 overlap the window
+    const int c = __popcll(__ballot(prel <= min(v0 + kWave - 1, total - 1)));
+    int koff = 0;
+    int prek = __builtin_amdgcn_readlane(prel, 0);
+    for (int i = 1; i < c; ++i) {
+      const int s = __builtin_amdgcn_readlane(prel, i);
+      const bool ge = vc >= s;
+      koff += ge ? 1 : 0;
+      prek = ge ? s : prek;
+    }
+    const int k = kb + koff;
+    kb = __builtin_amdgcn_readlane(k, kWave - 1);
+    const RunEntry<Real> e = W.run[k];
+    if constexpr (kF32) {
+      ref[0] = e.rx;
+      ref[1] = e.ry;
+      ref[2] = e.rz;
+    }
+    return e.g0 + (vc - prek);
+  }
+
+  // Unit separation (rotated into the line-of-sight frame) of a ring entry.
+  template <bool ROT>
+  static __device__ __forceinline__ void unit(const Primary& P, const V& e, Real& ux, Real& uy,
+                                              Real& uz) {
+    Real inv;
+    if constexpr (kF32) {
+      inv = __builtin_amdgcn_rsqf(fma_r(e.z, e.z, fma_r(e.y, e.y, e.x * e.x)));
+    } else {
+      inv = 1.0 / sqrt(e.x * e.x + e.y * e.y + e.z * e.z);
+    }
+    const Real dx = e.x * inv, dy = e.y * inv, dz = e.z * inv;
+    if constexpr (ROT) {
+      const Real* R = P.Rm;
+      ux = R[0] * dx + R[1] * dy + R[2] * dz;
+      uy = R[3] * dx + R[4] * dy + R[5] * dz;
+      uz = R[6] * dx + R[7] * dy + R[8] * dz;
+    } else {
+      ux = dx;
+      uy = dy;
+      uz = dz;
+    }
+  }
+
+  // One search of shell b over the annulus [r0, r1): every accepted pair is
+  // appended to the LDS ring as (separation, weight or index), and every full
+  // wave of pairs is handed to consume(entry, valid) (one pair per lane); the
+  // remainder at the end.  The position loads of the next window are issued
+  // before the current window is binned.
+  template <bool MINIMG, typename Consume>
+  static __device__ __forceinline__ unsigned search_shell(const PairArgs& a, Lds& W,
+                                                          const V* __restrict__ pos4,
+                                                          const Primary& P, int b, double r0,
+                                                          double r1, Consume&& consume) {
+    const int lane = threadIdx.x % kWave;
+    const int* __restrict__ cs = a.cell_start;
+    const double* p = P.p;
+    int c0[3] = {0, 0, 0}, c1[3] = {0, 0, 0};
+    for (int ax = 1; ax < 3; ++ax) {
+      if (a.tight[ax]) {
+        c0[ax] = 0;
+        c1[ax] = a.nc[ax] - 1;
+      } else {
+        c0[ax] = cell_floor(p[ax] - r1, a.lo[ax], a.inv_s[ax]);
+        c1[ax] = cell_floor(p[ax] + r1, a.lo[ax], a.inv_s[ax]);
+        if (!a.periodic) {
+          c0[ax] = min(max(c0[ax], 0), a.nc[ax] - 1);
+          c1[ax] = min(max(c1[ax], 0), a.nc[ax] - 1);
+        }
+      }
+    }
+    const int nyr = c1[1] - c0[1] + 1, nzr = c1[2] - c0[2] + 1;
+    const int nrows = nyr * nzr;
+    float lo2 = 0.0f, hi2 = 0.0f;
+    if constexpr (kF32) {
+      lo2 = a.r2_lo[b];
+      hi2 = a.r2_hi[b];
+    }
+    int head = 0, cnt = 0;
+    unsigned accepted = 0;
+    for (int rb = 0; rb < nrows; rb += kWave) {
+      int total = 0;
+      const int nrun = build_runs(a, cs, P, r0, r1, c0, nyr, rb, nrows, W, total);
+      if (total == 0) continue;
+      int kb = 0;
+      // bin one window and append its accepted pairs to the ring; consume a
+      // full wave of pairs when there is one
+      auto step = [&](const V& q, const Real* rref, int j, int v0) {
+        const bool valid = v0 + lane < total;
+        Real d[3];
+        bool acc;
+        if constexpr (kF32) {
+          const float* ref = MINIMG ? P.pref : rref;
+          float dx = __fsub_rn(q.x, ref[0]), dy = __fsub_rn(q.y, ref[1]),
+                dz = __fsub_rn(q.z, ref[2]);
+          if constexpr (MINIMG) {
+            dx = fma_r(-P.L[0], __builtin_rintf(__fmul_rn(dx, P.invL[0])), dx);
+            dy = fma_r(-P.L[1], __builtin_rintf(__fmul_rn(dy, P.invL[1])), dy);
+            dz = fma_r(-P.L[2], __builtin_rintf(__fmul_rn(dz, P.invL[2])), dz);
+          }
+          const float r2 = fma_r(dz, dz, fma_r(dy, dy, __fmul_rn(dx, dx)));
+          d[0] = dx;
+          d[1] = dy;
+          d[2] = dz;
+          acc = valid && r2 > lo2 && r2 < hi2;
+        } else {
+          double r2;
+          const int bin = P.bin64.classify(q, P.p, d, r2);
+          acc = valid && bin == b;
+        }
+        const unsigned long long m = __ballot(acc);
+        if (acc) {
+          V ent;
+          ent.x = d[0];
+          ent.y = d[1];
+          ent.z = d[2];
+          if constexpr (ADJOINT) {
+            ent.w = pack_index(j, Real(0));
+          } else {
+            ent.w = q.w;
+          }
+          W.ring[(head + cnt + lanes_below(m)) & (kRing - 1)] = ent;
+        }
+        const int got = __popcll(m);
+        cnt += got;
+        accepted += unsigned(got);
+        if (cnt >= kWave) {
+          wave_lds_fence();
+          const V ent = W.ring[(head + lane) & (kRing - 1)];
+          consume(ent, true);
+          head = (head + kWave) & (kRing - 1);
+          cnt -= kWave;
+        }
+      };
+      // two windows in flight: while one is binned the other's loads are
+      // outstanding (the buffers alternate, so no copy waits on a load).
+      // Windows past the end map every lane to the last candidate and accept
+      // nothing.
+      Real refa[3] = {P.pref[0], P.pref[1], P.pref[2]};
+      Real refb[3] = {P.pref[0], P.pref[1], P.pref[2]};
+      int ja = map_window(W, nrun, total, 0, kb, refa);
+      V qa = pos4[ja];
+      for (int v0 = 0; v0 < total; v0 += 2 * kWave) {
+        const int jb = map_window(W, nrun, total, v0 + kWave, kb, refb);
+        const V qb = pos4[jb];
+        step(qa, refa, ja, v0);
+        ja = map_window(W, nrun, total, v0 + 2 * kWave, kb, refa);
+        qa = pos4[ja];
+        step(qb, refb, jb, v0 + kWave);
+      }
+      wave_lds_fence();
+    }
+    if (cnt > 0) {
+      wave_lds_fence();
+      V ent;
+      if (lane < cnt) {
+        ent = W.ring[(head + lane) & (kRing - 1)];
+      } else {
+        ent.x = Real(0);
+        ent.y = Real(0);
+        ent.z = Real(1);
+        ent.w = ADJOINT ? pack_index(0, Real(0)) : Real(0);
+      }
+      consume(ent, lane < cnt);
+      wave_lds_fence();
+    }
+    return accepted;
+  }
+
+  // All chunks (forward) or the adjoint of shell b, with the line-of-sight
+  // rotation and the minimum-image mode fixed at compile time.
+  template <bool ROT, bool MINIMG>
+  static __device__ __forceinline__ unsigned shell(const PairArgs& a, Lds& W,
+                                                   const V* __restrict__ pos4, const Primary& P,
+                                                   int b, double r0, double r1, long long row,
+                                                   double w_prim) {
+    unsigned got = 0;
+    if constexpr (!ADJOINT) {
+      using CL = typename Chunks<Real, BASIS>::type;
+      bool first = true;
+      for_each_chunk(CL{}, [&](auto* tag) {
+        using Chunk = std::remove_pointer_t<decltype(tag)>;
+        Chunk ch;
+        ch.zero();
+        const unsigned g = search_shell<MINIMG>(a, W, pos4, P, b, r0, r1,
+                                                [&](const V& e, bool) {
+                                                  Real ux, uy, uz;
+                                                  unit<ROT>(P, e, ux, uy, uz);
+                                                  ch.add(ux, uy, uz, e.w);
+                                                });
+        if (first) got = g;
+        first = false;
+        reduce_store(W, ch);
+      });
+      wave_lds_fence();
+      convert(a, W, b, row);
+      wave_lds_fence();
+    } else {
+      load_gcoef(a, W, b, row);
+      got = search_shell<MINIMG>(a, W, pos4, P, b, r0, r1, [&](const V& e, bool valid) {
+        Real ux, uy, uz;
+        unit<ROT>(P, e, ux, uy, uz);
+        scatter_one(a, W, ux, uy, uz, unpack_index(e.w), valid, w_prim);
+      });
+      wave_lds_fence();
+    }
+    return got;
   }
 
   static __device__ __forceinline__ void run(const PairArgs& a) {
@@ -322,240 +574,94 @@ struct PairKernel {
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x % kWave;
     Lds& W = lds[wid];
-    const int gwave = blockIdx.x * kWavesPerBlock + wid;
-    int* scratch = a.scratch + size_t(gwave) * 2 * a.scratch_per_wave;
     const V* __restrict__ pos4 = static_cast<const V*>(a.pos4);
-    const int* __restrict__ cs = a.cell_start;
-    const long long P = min(a.p_count, (long long)(*a.nprim) - a.p_begin);
+    const long long NP = min(a.p_count, (long long)(*a.nprim) - a.p_begin);
     const int nb = a.nbins;
-    const int S = a.scratch_per_wave;
+    const double margin = a.rmax_search - a.rmax;
     unsigned long long my_pairs = 0;
 
     while (true) {
-      int q = 0;
-      if (lane == 0) q = atomicAdd(a.queue, 1);
-      q = uniform_int(__shfl(q, 0));
-      if (q >= P) break;
-      const int slot = uniform_int(a.plist[a.p_begin + q]);
+      int qi = 0;
+      if (lane == 0) qi = atomicAdd(a.queue, 1);
+      qi = uniform_int(__shfl(qi, 0));
+      if (qi >= NP) break;
+      const int slot = uniform_int(a.plist[a.p_begin + qi]);
       const V pv = pos4[slot];
-      double p[3] = {uniform_double(double(pv.x)), uniform_double(double(pv.y)),
-                     uniform_double(double(pv.z))};
-
-      // line-of-sight frame (Rodrigues rotation taking the LOS to +z)
-      Real Rm[9] = {Real(1), Real(0), Real(0), Real(0), Real(1), Real(0), Real(0), Real(0), Real(1)};
-      if (a.los == G3PCF_LOS_OBSERVER) {
-        double n[3] = {p[0] - a.obs[0], p[1] - a.obs[1], p[2] - a.obs[2]};
-        const double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-        if (nn > 0.0) {
-          for (int c = 0; c < 3; ++c) n[c] /= nn;
-          const double c = n[2];
-          if (c < -1.0 + 1e-12) {
-            Rm[4] = Real(-1);
-            Rm[8] = Real(-1);
-          } else {
-            const double vx = n[1], vy = -n[0];  // v = n x z
-            const double f = 1.0 / (1.0 + c);
-            const double vv = vx * vx + vy * vy;
-            // R = I + [v]x + (v v^T - |v|^2 I) / (1 + c), v_z = 0
-            Rm[0] = Real(1.0 + (vx * vx - vv) * f);
-            Rm[1] = Real(vx * vy * f);
-            Rm[2] = Real(vy);
-            Rm[3] = Real(vx * vy * f);
-            Rm[4] = Real(1.0 + (vy * vy - vv) * f);
-            Rm[5] = Real(-vx);
-            Rm[6] = Real(-vy);
-            Rm[7] = Real(vx);
-            Rm[8] = Real(1.0 - vv * f);
-          }
-        }
-      }
-
-      PairTest<Real> T;
+      Primary P;
+      P.p[0] = uniform_double(double(pv.x));
+      P.p[1] = uniform_double(double(pv.y));
+      P.p[2] = uniform_double(double(pv.z));
+      frame(a, P);
       for (int c = 0; c < 3; ++c) {
-        T.L[c] = Real(a.L[c]);
-        T.invL[c] = Real(1.0 / a.L[c]);
-        T.ref[c] = Real(p[c]);
+        P.L[c] = Real(a.L[c]);
+        P.invL[c] = Real(1.0 / a.L[c]);
+        P.pref[c] = Real(P.p[c]);
+        P.bin64.L[c] = a.L[c];
       }
-      T.minimg = a.periodic && (std::is_same<Real, double>::value || a.tight[0] || a.tight[1] ||
-                                a.tight[2]);
-      T.r2max = Real(a.rmax * a.rmax);
-      T.nb_over_r = Real(double(nb) / a.rmax);
-      T.nbins = nb;
-      T.rmax_d = a.rmax;
+      // FP64 always measures from the primary with the minimum image (the
+      // plain definition); FP32 only where a search window can wrap onto itself
+      P.minimg = a.periodic && (!kF32 || a.tight[0] || a.tight[1] || a.tight[2]);
+      P.bin64.minimg = P.minimg;
+      P.bin64.r2max = a.rmax * a.rmax;
+      P.bin64.nbins = nb;
+      P.bin64.rmax = a.rmax;
 
-      // ---- pass 0: candidate runs.  Pass 1: one search that counts the
-      // accepted secondaries per shell and appends (index | shell << 27) to an
-      // unsorted list in the second half of the scratch.
-      build_segments(a, cs, p, W);
-      if (lane < nb) W.cnt[lane] = 0;
-      wave_lds_fence();
-      unsigned* unsorted = reinterpret_cast<unsigned*>(scratch + S);
-      int appended = 0;
-      scan(a, W, pos4, p, T, [&](int j, int b) {
-        const bool hit = b >= 0;
-        if (hit) atomicAdd(&W.cnt[b], 1);
-        const unsigned long long m = __ballot(hit);
-        const int at = appended + lanes_below(m);
-        if (hit && at < S && a.packed_lists) unsorted[at] = unsigned(j) | (unsigned(b) << kShellShift);
-        appended += __popcll(m);
-      });
-      wave_lds_fence();
-
-      int total = 0;
-      for (int b = 0; b < nb; ++b) total += W.cnt[b];
-      my_pairs += (unsigned long long)total;
-
-      const long long row = q;  // row of A within this pair-block
+      const long long row = qi;  // row of A within this pair-block
       double w_prim = 0.0;
       if constexpr (ADJOINT) w_prim = a.wsort[slot];
 
-      if (total <= S && a.packed_lists) {
-        // ---- pass 2: counting sort of the unsorted list by shell
-        if (lane == 0) {
-          int off = 0;
-          for (int b = 0; b < nb; ++b) {
-            W.off[b] = off;
-            W.cur[b] = 0;
-            off += W.cnt[b];
-          }
+      for (int b = 0; b < nb; ++b) {
+        // annulus of shell b, widened by the search margin on both sides
+        const double r0 = fmax(0.0, b * a.rmax / nb - margin);
+        const double r1 = (b + 1 == nb) ? a.rmax_search : (b + 1) * a.rmax / nb + margin;
+        if (P.rotate) {
+          if (kF32 && P.minimg)
+            my_pairs += shell<true, kF32>(a, W, pos4, P, b, r0, r1, row, w_prim);
+          else
+            my_pairs += shell<true, false>(a, W, pos4, P, b, r0, r1, row, w_prim);
+        } else {
+          if (kF32 && P.minimg)
+            my_pairs += shell<false, kF32>(a, W, pos4, P, b, r0, r1, row, w_prim);
+          else
+            my_pairs += shell<false, false>(a, W, pos4, P, b, r0, r1, row, w_prim);
         }
-        wave_lds_fence();
-        // eight entries per lane in flight: loads, then the LDS slot atomics,
-        // then the stores
-        constexpr int kSortUnroll = 8;
-        for (int base = 0; base < total; base += kSortUnroll * kWave) {
-          unsigned e[kSortUnroll];
-          int at[kSortUnroll];
-#pragma unroll
-          for (int u = 0; u < kSortUnroll; ++u)
-            e[u] = unsorted[min(base + u * kWave + lane, total - 1)];
-#pragma unroll
-          for (int u = 0; u < kSortUnroll; ++u) {
-            const bool ok = base + u * kWave + lane < total;
-            at[u] = ok ? atomicAdd(&W.cur[e[u] >> kShellShift], 1) : 0;
-          }
-#pragma unroll
-          for (int u = 0; u < kSortUnroll; ++u) {
-            if (base + u * kWave + lane < total)
-              scratch[W.off[e[u] >> kShellShift] + at[u]] = int(e[u] & ((1u << kShellShift) - 1u));
-          }
-        }
-        wave_lds_fence();
-        // ---- pass 3: every shell from its list
-        for (int b = 0; b < nb; ++b) {
-          const int cb = uniform_int(W.cnt[b]);
-          const int* list = scratch + uniform_int(W.off[b]);
-          shell(a, W, pos4, p, Rm, b, list, cb, row, w_prim);
-        }
-        continue;
-      }
-
-      // ---- more pairs than the scratch holds: groups of shells that fit,
-      // each filled by a repeated search
-      int b = 0;
-      while (b < nb) {
-        const int cb = uniform_int(W.cnt[b]);
-        if (cb > S) {
-          process_sliced(a, W, scratch, pos4, p, T, Rm, b, cb, row, w_prim);
-          ++b;
-          continue;
-        }
-        int e = b, tot = 0;
-        while (e < nb) {
-          const int ce = uniform_int(W.cnt[e]);
-          if (tot + ce > S) break;
-          if (lane == 0) {
-            W.off[e] = tot;
-            W.cur[e] = 0;
-          }
-          tot += ce;
-          ++e;
-        }
-        wave_lds_fence();
-        if (tot > 0) {
-          const int gb0 = b, gb1 = e;
-          scan(a, W, pos4, p, T, [&](int j, int bb) {
-            if (bb >= gb0 && bb < gb1) {
-              const int at = atomicAdd(&W.cur[bb], 1);
-              if (at < W.cnt[bb]) scratch[W.off[bb] + at] = j;
-            }
-          });
-          wave_lds_fence();
-        }
-        for (int bb = b; bb < e; ++bb) {
-          const int cbb = uniform_int(W.cnt[bb]);
-          const int* list = scratch + uniform_int(W.off[bb]);
-          shell(a, W, pos4, p, Rm, bb, list, cbb, row, w_prim);
-        }
-        b = e;
       }
     }
 
     if (lane == 0 && my_pairs) atomicAdd(a.pairs, my_pairs);
   }
 
-  // Unit separation (rotated) and weight from a loaded secondary.
-  static __device__ __forceinline__ void unit_pair(const PairArgs& a, const V& qv, bool valid,
-                                                   const double p[3], const Real* Rm, Real& ux,
-                                                   Real& uy, Real& uz, Real& w) {
-    Real dx = qv.x - Real(p[0]);
-    Real dy = qv.y - Real(p[1]);
-    Real dz = qv.z - Real(p[2]);
-    if (a.periodic) {
-      dx -= Real(a.L[0]) * rint(dx * Real(1.0 / a.L[0]));
-      dy -= Real(a.L[1]) * rint(dy * Real(1.0 / a.L[1]));
-      dz -= Real(a.L[2]) * rint(dz * Real(1.0 / a.L[2]));
+  // Line-of-sight frame of the primary: identity (z mode) or the Rodrigues
+  // rotation taking the direction from the observer to +z.
+  static __device__ __forceinline__ void frame(const PairArgs& a, Primary& P) {
+    for (int i = 0; i < 9; ++i) P.Rm[i] = Real((i % 4 == 0) ? 1 : 0);
+    P.rotate = false;
+    if (a.los != G3PCF_LOS_OBSERVER) return;
+    P.rotate = true;
+    const double* p = P.p;
+    double n[3] = {p[0] - a.obs[0], p[1] - a.obs[1], p[2] - a.obs[2]};
+    const double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    if (!(nn > 0.0)) return;
+    for (int c = 0; c < 3; ++c) n[c] /= nn;
+    const double c = n[2];
+    if (c < -1.0 + 1e-12) {
+      P.Rm[4] = Real(-1);
+      P.Rm[8] = Real(-1);
+      return;
     }
-    w = valid ? qv.w : Real(0);
-    if (!valid) {
-      dx = Real(0);
-      dy = Real(0);
-      dz = Real(1);
-    }
-    Real inv;
-    if constexpr (std::is_same<Real, float>::value) {
-      inv = __builtin_amdgcn_rsqf(fma_r(dz, dz, fma_r(dy, dy, dx * dx)));
-    } else {
-      inv = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
-    }
-    dx *= inv;
-    dy *= inv;
-    dz *= inv;
-    if (a.los == G3PCF_LOS_OBSERVER) {
-      ux = Rm[0] * dx + Rm[1] * dy + Rm[2] * dz;
-      uy = Rm[3] * dx + Rm[4] * dy + Rm[5] * dz;
-      uz = Rm[6] * dx + Rm[7] * dy + Rm[8] * dz;
-    } else {
-      ux = dx;
-      uy = dy;
-      uz = dz;
-    }
-  }
-
-  // Stream a list with the gather of the next pair and the index two pairs
-  // ahead already in flight; body(ux, uy, uz, w, j, valid) per lane.
-  template <typename Body>
-  static __device__ __forceinline__ void stream(const PairArgs& a, const V* __restrict__ pos4,
-                                                const double p[3], const Real* Rm,
-                                                const int* __restrict__ list, int count,
-                                                Body&& body) {
-    if (count <= 0) return;
-    const int lane = threadIdx.x % kWave;
-    const int last = count - 1;
-    int j0 = list[min(lane, last)];
-    int j1 = list[min(kWave + lane, last)];
-    V q0 = pos4[j0];
-    for (int base = 0; base < count; base += kWave) {
-      const V qc = q0;
-      const int jc = j0;
-      const bool valid = base + lane < count;
-      q0 = pos4[j1];
-      j0 = j1;
-      j1 = list[min(base + 2 * kWave + lane, last)];
-      Real ux, uy, uz, w;
-      unit_pair(a, qc, valid, p, Rm, ux, uy, uz, w);
-      body(ux, uy, uz, w, jc, valid);
-    }
+    const double vx = n[1], vy = -n[0];  // v = n x z
+    const double f = 1.0 / (1.0 + c);
+    const double vv = vx * vx + vy * vy;
+    // R = I + [v]x + (v v^T - |v|^2 I) / (1 + c), v_z = 0
+    P.Rm[0] = Real(1.0 + (vx * vx - vv) * f);
+    P.Rm[1] = Real(vx * vy * f);
+    P.Rm[2] = Real(vy);
+    P.Rm[3] = Real(vx * vy * f);
+    P.Rm[4] = Real(1.0 + (vy * vy - vv) * f);
+    P.Rm[5] = Real(-vx);
+    P.Rm[6] = Real(-vy);
+    P.Rm[7] = Real(vx);
+    P.Rm[8] = Real(1.0 - vv * f);
   }
 
   // Wave sums of a chunk's accumulators into W.M, four at a time: row sums by
@@ -585,8 +691,8 @@ struct PairKernel {
   }
 
   // Convert the shell's monomial sums in W.M to a_lm (FP64) and write them.
-  static __device__ __forceinline__ void convert(const PairArgs& a, const Lds& W,
-                                                 int b, long long row) {
+  static __device__ __forceinline__ void convert(const PairArgs& a, const Lds& W, int b,
+                                                 long long row) {
     const int lane = threadIdx.x % kWave;
     const ConvTable& t = g_conv[BASIS];
     const RowLayout& L = a.lay;
@@ -611,93 +717,20 @@ struct PairKernel {
     wave_lds_fence();
   }
 
-  // Adjoint scatter over a list: per pair the full polynomial
-  // sum_t g_t mono_t(u) in FP64 (its coefficients cancel strongly at l = 10),
-  // with the coefficients read from LDS through an offset the compiler cannot
-  // hoist out of the loop, so they do not occupy registers.
-  static __device__ __forceinline__ void scatter(const PairArgs& a, const Lds& W,
-                                                 const V* __restrict__ pos4, const double p[3],
-                                                 const Real* Rm, const int* list, int count,
-                                                 double w_prim) {
+  // Adjoint for one pair per lane: the full polynomial sum_t g_t mono_t(u) in
+  // FP64 (its coefficients cancel strongly at l = 10), with the coefficients
+  // read from LDS through an offset the compiler cannot hoist out of the
+  // loop, so they do not occupy registers.
+  static __device__ __forceinline__ void scatter_one(const PairArgs& a, const Lds& W, Real ux,
+                                                     Real uy, Real uz, int j, bool valid,
+                                                     double w_prim) {
     using Poly = std::conditional_t<BASIS == G3PCF_BASIS_SPIN, SpinChunk<double, 0, kDeg>,
                                     CartChunk<double, (1u << (kDeg + 1)) - 1>>;
-    stream(a, pos4, p, Rm, list, count, [&](Real ux, Real uy, Real uz, Real, int j, bool valid) {
-      int off = 0;
-      asm volatile("" : "+v"(off));
-      const double v = Poly::poly(double(ux), double(uy), double(uz),
-                                  [&](int t) { return W.M[t + off]; });
-      if (valid) unsafeAtomicAdd(&a.grad_w[j], w_prim * v);
-    });
-  }
-
-  // Forward: all chunks of one shell from a list, then conversion.
-  static __device__ __forceinline__ void shell(const PairArgs& a, Lds& W,
-                                               const V* __restrict__ pos4, const double p[3],
-                                               const Real* Rm, int b, const int* list,
-                                               int count, long long row, double w_prim) {
-    using CL = typename Chunks<Real, BASIS>::type;
-    if constexpr (!ADJOINT) {
-      for_each_chunk(CL{}, [&](auto* tag) {
-        using Chunk = std::remove_pointer_t<decltype(tag)>;
-        Chunk ch;
-        ch.zero();
-        stream(a, pos4, p, Rm, list, count,
-               [&](Real ux, Real uy, Real uz, Real w, int, bool) { ch.add(ux, uy, uz, w); });
-        reduce_store(W, ch);
-      });
-      wave_lds_fence();
-      convert(a, W, b, row);
-      wave_lds_fence();
-    } else {
-      if (count == 0) return;
-      load_gcoef(a, W, b, row);
-      scatter(a, W, pos4, p, Rm, list, count, w_prim);
-      wave_lds_fence();
-    }
-  }
-
-  // A shell with more pairs than the scratch holds: slices of S pairs in a
-  // deterministic order (ballot ranks), the search repeated per slice.
-  static __device__ void process_sliced(const PairArgs& a, Lds& W, int* scratch,
-                                        const V* __restrict__ pos4, const double p[3],
-                                        PairTest<Real>& T, const Real* Rm, int b, int cb,
-                                        long long row, double w_prim) {
-    const int S = a.scratch_per_wave;
-    auto fill_slice = [&](int s0) {
-      int rank_base = 0;
-      scan(a, W, pos4, p, T, [&](int j, int bb) {
-        const bool hit = (bb == b);
-        const unsigned long long m = __ballot(hit);
-        const int r = rank_base + lanes_below(m);
-        if (hit && r >= s0 && r < s0 + S) scratch[r - s0] = j;
-        rank_base += __popcll(m);
-      });
-      wave_lds_fence();
-    };
-    using CL = typename Chunks<Real, BASIS>::type;
-    if constexpr (!ADJOINT) {
-      for_each_chunk(CL{}, [&](auto* tag) {
-        using Chunk = std::remove_pointer_t<decltype(tag)>;
-        Chunk ch;
-        ch.zero();
-        for (int s0 = 0; s0 < cb; s0 += S) {
-          fill_slice(s0);
-          stream(a, pos4, p, Rm, scratch, min(S, cb - s0),
-                 [&](Real ux, Real uy, Real uz, Real w, int, bool) { ch.add(ux, uy, uz, w); });
-        }
-        reduce_store(W, ch);
-      });
-      wave_lds_fence();
-      convert(a, W, b, row);
-      wave_lds_fence();
-    } else {
-      load_gcoef(a, W, b, row);
-      for (int s0 = 0; s0 < cb; s0 += S) {
-        fill_slice(s0);
-        scatter(a, W, pos4, p, Rm, scratch, min(S, cb - s0), w_prim);
-      }
-      wave_lds_fence();
-    }
+    int off = 0;
+    asm volatile("" : "+v"(off));
+    const double v =
+        Poly::poly(double(ux), double(uy), double(uz), [&](int t) { return W.M[t + off]; });
+    if (valid) unsafeAtomicAdd(&a.grad_w[j], w_prim * v);
   }
 };
 
