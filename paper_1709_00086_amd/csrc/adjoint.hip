@@ -30,8 +30,6 @@ namespace {
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
-constexpr int kTile = 16;
-
 __device__ __forceinline__ size_t zidx(int lmax, int nb, int m, int l, int lp, int b1, int b2) {
   const size_t L1 = size_t(lmax) + 1;
   return ((((size_t(m) * L1 + l) * L1 + lp) * nb + b1) * nb + b2) * 2;
@@ -41,7 +39,6 @@ struct AdjDims {
   int nm;
   int W[kDeg + 1], off[kDeg + 1], d[kDeg + 1];
   int cw[kDeg + 2];     // offset of M_H^m in the matrix buffer
-  int ctiles[kDeg + 2]; // cumulative column tiles
   int rowW, nb, lmax;
 };
 
@@ -51,18 +48,15 @@ AdjDims make_adj_dims(const RowLayout& L) {
   d.rowW = L.W;
   d.nb = L.nb;
   d.lmax = L.lmax;
-  int cw = 0, ct = 0;
+  int cw = 0;
   for (int m = 0; m < d.nm; ++m) {
     d.W[m] = L.wm[m];
     d.off[m] = L.off[m];
     d.d[m] = L.d[m];
     d.cw[m] = cw;
-    d.ctiles[m] = ct;
     cw += L.wm[m] * L.wm[m];
-    ct += (L.wm[m] + kTile - 1) / kTile;
   }
   d.cw[d.nm] = cw;
-  d.ctiles[d.nm] = ct;
   return d;
 }
 
@@ -92,44 +86,100 @@ __global__ void k_build_mh(const double* __restrict__ gz, AdjDims d, double* __r
   MHt[idx] = v;
 }
 
-// H rows = X rows times M_H^T, per m, on FP64 MFMA.  One wave per
-// (16 primaries, m, 16 output columns).  Lane l supplies A[i = l % 16][k = l / 16]
-// = X[row i][k] and B[k = l / 16][j = l % 16] = M_H^T[k][j]; the FP64 result
-// holds row g + 4 r (g = l / 16) in register r.
+// H rows = X rows times M_H^T, per m, on FP64 MFMA.  One workgroup per
+// (64 primaries, 64 output columns of one m): each step stages a 64 x 16 slice
+// of X and a 16 x 64 slice of M_H^T in LDS, and each wave accumulates a 32 x 32
+// quadrant as 2 x 2 MFMA tiles.  Lane l supplies A[i = l % 16][k = l / 16] and
+// B[k = l / 16][j = l % 16]; the FP64 result holds row g + 4 r (g = l / 16) in
+// register r.
+constexpr int kHT = 64;   // rows and columns of a macro tile
+constexpr int kHK = 16;   // k per step
+
+struct HDims {
+  int nm;
+  int W[kDeg + 1], off[kDeg + 1];
+  int cw[kDeg + 1];
+  int ct[kDeg + 2];       // cumulative 64-column tiles
+  int rowW;
+};
+
+HDims make_hdims(const RowLayout& L) {
+  HDims d{};
+  d.nm = L.lmax + 1;
+  d.rowW = L.W;
+  int cw = 0, ct = 0;
+  for (int m = 0; m < d.nm; ++m) {
+    d.W[m] = L.wm[m];
+    d.off[m] = L.off[m];
+    d.cw[m] = cw;
+    d.ct[m] = ct;
+    cw += L.wm[m] * L.wm[m];
+    ct += (L.wm[m] + kHT - 1) / kHT;
+  }
+  d.ct[d.nm] = ct;
+  return d;
+}
+
 __global__ __launch_bounds__(256) void k_h_gemm(const double* __restrict__ A,
-                                                const double* __restrict__ MHt, AdjDims d,
-                                                long long rows, double* __restrict__ H) {
-  const long long wave = (long long)blockIdx.x * 4 + threadIdx.x / kWave;
-  const int lane = threadIdx.x % kWave;
-  const int nct = d.ctiles[d.nm];
-  const long long rt = wave / nct;
-  const int ct = int(wave % nct);
-  if (rt * kTile >= rows) return;
+                                                const double* __restrict__ MHt, HDims d,
+                                                const long long* __restrict__ nprim,
+                                                long long p_begin, long long p_count,
+                                                double* __restrict__ H) {
+  __shared__ double Xs[kHT][kHK + 1];   // odd row stride: rows spread over banks
+  __shared__ double Ms[kHK][kHT + 8];
+  const int tid = threadIdx.x;
+  const int lane = tid % kWave, wv = tid / kWave;
+  const long long rows = min(p_count, (long long)(*nprim) - p_begin);
+  const long long R0 = (long long)blockIdx.y * kHT;
+  if (R0 >= rows) return;
   int m = 0;
-  while (m + 1 < d.nm && ct >= d.ctiles[m + 1]) ++m;
+  while (m + 1 < d.nm && int(blockIdx.x) >= d.ct[m + 1]) ++m;
   const int W = d.W[m];
-  const int j0 = (ct - d.ctiles[m]) * kTile;
-  const int il = lane % 16, g = lane / 16;
-  const long long r = rt * kTile + il;
-  const bool rv = r < rows;
-  const double* xrow = A + (rv ? r : 0) * (long long)d.rowW + d.off[m];
+  const int J0 = (int(blockIdx.x) - d.ct[m]) * kHT;
   const double* B = MHt + d.cw[m];
-  const int j = j0 + il;
-  double4_t acc = {0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < W; k0 += 4) {
-    const int k = k0 + g;
-    const double av = (rv && k < W) ? xrow[k] : 0.0;
-    const double bv = (k < W && j < W) ? B[k * W + j] : 0.0;
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+  // staging coordinates: X (row, 4 k's), M (k, 4 columns)
+  const int xr = tid / 4, xk = (tid % 4) * 4;
+  const int mk = tid / 16, mc = (tid % 16) * 4;
+  const long long xrow = R0 + xr;
+  const double* xp = A + (xrow < rows ? xrow : R0) * (long long)d.rowW + d.off[m];
+  const int qi = (wv >> 1) * 32, qj = (wv & 1) * 32;
+  const int li = lane % 16, g = lane / 16;
+  double4_t acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = double4_t{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < W; k0 += kHK) {
+    for (int c = 0; c < 4; ++c) {
+      const int k = k0 + xk + c;
+      Xs[xr][xk + c] = (xrow < rows && k < W) ? xp[k] : 0.0;
+      const int kk = k0 + mk, j = J0 + mc + c;
+      Ms[mk][mc + c] = (kk < W && j < W) ? B[(long long)kk * W + j] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kHK; k += 4) {
+      double xa[2], yb[2];
+      for (int a = 0; a < 2; ++a) xa[a] = Xs[qi + a * 16 + li][k + g];
+      for (int b = 0; b < 2; ++b) yb[b] = Ms[k + g][qj + b * 16 + li];
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[a], yb[b], acc[a][b], 0, 0, 0);
+    }
+    __syncthreads();
   }
-  for (int q = 0; q < 4; ++q) {
-    const long long rr = rt * kTile + g + 4 * q;
-    if (rr < rows && j < W) H[rr * d.rowW + d.off[m] + j] = acc[q];
-  }
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int q = 0; q < 4; ++q) {
+        const long long rr = R0 + qi + a * 16 + g + 4 * q;
+        const int j = J0 + qj + b * 16 + li;
+        if (rr < rows && j < W) H[rr * d.rowW + d.off[m] + j] = acc[a][b][q];
+      }
 }
 
 // Per primary: the primary term Re(a^T H) / 2 and the coefficients g_t(b).
+// One thread per monomial term: its conversion entries are read once and
+// applied to every shell.
 constexpr int kFinThreads = 128;
+constexpr int kFinShells = 8;   // shells per pass over a term's entries
 
 __global__ __launch_bounds__(kFinThreads) void k_adj_finish(AdjArgs a, AdjDims d) {
   const long long row = blockIdx.x;
@@ -138,8 +188,9 @@ __global__ __launch_bounds__(kFinThreads) void k_adj_finish(AdjArgs a, AdjDims d
   const int slot = a.plist[a.p_begin + row];
   const double* x = a.A + row * (long long)d.rowW;
   const double* h = a.H + row * (long long)d.rowW;
-  __shared__ double hs[4096];
-  __shared__ double red[kFinThreads];
+  extern __shared__ double fin_smem[];
+  double* red = fin_smem;                // [kFinThreads]
+  double* hs = fin_smem + kFinThreads;   // [rowW]
   double prim = 0.0;
   for (int c = threadIdx.x; c < d.rowW; c += blockDim.x) {
     const double hv = h[c];
@@ -162,18 +213,24 @@ __global__ __launch_bounds__(kFinThreads) void k_adj_finish(AdjArgs a, AdjDims d
   const int nb = d.nb;
   const int T = (a.basis == G3PCF_BASIS_SPIN) ? kTermsSpin : kTermsCart;
   double* gout = a.gcoef + row * (long long)nb * T;
-  for (int o = threadIdx.x; o < nb * T; o += blockDim.x) {
-    const int b = o / T, term = o % T;
-    double s = 0.0;
-    for (int e = t.trowptr[term]; e < t.trowptr[term + 1]; ++e) {
-      const int out = t.tout[e];
-      const int l = t.out_l[out];
-      if (l > d.lmax) continue;
-      const int m = t.out_m[out], part = t.out_part[out];
-      const int col = d.off[m] + (l - m) * nb + b;
-      s += (part == 0) ? t.tcoef[e] * hs[col] : -t.tcoef[e] * hs[col + d.d[m]];
+  for (int term = threadIdx.x; term < T; term += blockDim.x) {
+    const int e0 = t.trowptr[term], e1 = t.trowptr[term + 1];
+    for (int b0 = 0; b0 < nb; b0 += kFinShells) {
+      double sacc[kFinShells];
+      for (int q = 0; q < kFinShells; ++q) sacc[q] = 0.0;
+      for (int e = e0; e < e1; ++e) {
+        const int out = t.tout[e];
+        const int l = t.out_l[out];
+        if (l > d.lmax) continue;
+        const int m = t.out_m[out], part = t.out_part[out];
+        const int col = d.off[m] + (l - m) * nb + (part ? d.d[m] : 0);
+        const double c = part ? -t.tcoef[e] : t.tcoef[e];
+        for (int q = 0; q < kFinShells; ++q)
+          if (b0 + q < nb) sacc[q] += c * hs[col + b0 + q];
+      }
+      for (int q = 0; q < kFinShells; ++q)
+        if (b0 + q < nb) gout[(b0 + q) * T + term] = sacc[q];
     }
-    gout[o] = s;
   }
 }
 
@@ -199,14 +256,14 @@ hipError_t launch_adj_matrix(const double* gz, const RowLayout& L, double* MHt,
 
 hipError_t launch_adj_coef(const AdjArgs& a, hipStream_t st) {
   const AdjDims d = make_adj_dims(a.lay);
-  if (d.rowW > 4096) return hipErrorInvalidValue;
-  const long long row_tiles = (a.p_count + kTile - 1) / kTile;
-  const long long waves = row_tiles * d.ctiles[d.nm];
-  hipLaunchKernelGGL(k_h_gemm, dim3(unsigned((waves + 3) / 4)), dim3(256), 0, st, a.A, a.MHt,
-                     d, a.p_count, a.H);
+  const HDims hd = make_hdims(a.lay);
+  const long long row_tiles = (a.p_count + kHT - 1) / kHT;
+  hipLaunchKernelGGL(k_h_gemm, dim3(unsigned(hd.ct[hd.nm]), unsigned(row_tiles)), dim3(256), 0,
+                     st, a.A, a.MHt, hd, a.nprim, a.p_begin, a.p_count, a.H);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_adj_finish, dim3(unsigned(a.p_count)), dim3(kFinThreads), 0, st, a, d);
+  const size_t shm = size_t(kFinThreads + d.rowW) * sizeof(double);
+  hipLaunchKernelGGL(k_adj_finish, dim3(unsigned(a.p_count)), dim3(kFinThreads), shm, st, a, d);
   return hipGetLastError();
 }
 

@@ -61,11 +61,12 @@ size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Ws {
   size_t pos4, tmp4, cid, perm, tmp_perm, wsort, cell_start, cell_count, flags, plist, scan,
-      counters, A, C, ops, gcoef, gsort, mht, hrows;
+      counters, spill, A, C, ops, gcoef, gsort, mht, hrows;
   size_t scan_bytes;
   size_t total;
   int64_t PB;   // primaries per pair-block
   int Kp;       // padded rows of a zeta sub-block (bf16 operands)
+  int spill_cap;  // spill-list entries per wave (0: none)
   Grid grid;
   RowLayout lay;
 };
@@ -99,8 +100,12 @@ Ws plan(const g3pcf_problem& p, int backward) {
   w.plist = take(size_t(n) * 4);
   w.scan = take(w.scan_bytes);
   w.counters = take(256);
+  // per-wave spill lists for bases accumulated in several register chunks
+  const bool multi = fp64 || p.basis == G3PCF_BASIS_CARTESIAN;
+  w.spill = take(multi ? size_t(kPairWaves) * kSpillCap * 4 : 0);
+  w.spill_cap = multi ? kSpillCap : 0;
   w.A = take(size_t(w.PB) * w.lay.W * 8);
-  w.C = take(size_t(kZetaSplitK) * sum_wm2(w.lay) * 8);
+  w.C = take(zeta_partial_doubles(w.lay) * 8);
   w.ops = (!backward && p.zeta_prec == G3PCF_PREC_BF16X3) ? take(size_t(6) * w.lay.W * w.Kp * 2)
                                                            : take(0);
   if (backward) {
@@ -204,6 +209,8 @@ PairArgs pair_args(const g3pcf_problem& p, const Ws& w, void* ws) {
   a.cell_start = at<int>(ws, w.cell_start);
   a.plist = at<int>(ws, w.plist);
   a.nprim = &c->nprim;
+  a.spill = at<int>(ws, w.spill);
+  a.spill_cap = w.spill_cap;
   a.queue = &c->queue;
   a.pairs = &c->pairs;
   for (int k = 0; k < 3; ++k) {
@@ -361,23 +368,21 @@ int g3pcf_forward(const g3pcf_problem* prob, double* zeta, void* ws, size_t ws_b
         return hip_fail(e, "pair kernel");
     }
     StageScope scz(p.trace, G3PCF_STAGE_ZETA, st);
-    for (int64_t s0 = 0; s0 < a.p_count; s0 += kZetaBlock) {
-      ZetaArgs z{};
-      z.A = a.A;
-      z.wsort = a.wsort;
-      z.plist = a.plist;
-      z.nprim = &c->nprim;
-      z.row_begin = b0;
-      z.sub_begin = s0;
-      z.K = int(std::min<int64_t>(kZetaBlock, a.p_count - s0));
-      z.lay = w.lay;
-      z.ops = at<void>(ws, w.ops);
-      z.C32 = at<float>(ws, w.C);
-      z.C64 = at<double>(ws, w.C);
-      z.zeta = zeta;
-      z.prec = p.zeta_prec;
-      if ((e = launch_zeta_block(z, st)) != hipSuccess) return hip_fail(e, "zeta block");
-    }
+    ZetaArgs z{};
+    z.A = a.A;
+    z.wsort = a.wsort;
+    z.plist = a.plist;
+    z.nprim = &c->nprim;
+    z.row_begin = b0;
+    z.sub_begin = 0;
+    z.K = a.p_count;
+    z.lay = w.lay;
+    z.ops = at<void>(ws, w.ops);
+    z.C32 = at<float>(ws, w.C);
+    z.C64 = at<double>(ws, w.C);
+    z.zeta = zeta;
+    z.prec = p.zeta_prec;
+    if ((e = launch_zeta_pairblock(z, st)) != hipSuccess) return hip_fail(e, "zeta");
   }
   return finish_pairs(p, w, ws, st);
 }

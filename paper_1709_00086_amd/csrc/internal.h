@@ -26,6 +26,9 @@ constexpr int kZetaBlock = 4096;
 constexpr int kZetaSplitK = 4;
 // Persistent waves of the pair kernel.
 constexpr int kPairWaves = 4096;
+// Spill-list entries per wave: a shell's secondaries kept for the later
+// accumulator chunks of a multi-chunk basis.
+constexpr int kSpillCap = 1 << 14;
 // Maximum pair-block (primaries whose a_lm rows are held at once).
 constexpr int kPairBlockMax = 131072;
 
@@ -77,6 +80,8 @@ struct PairArgs {
   const int* cell_start;     // [ncell + 1]
   const int* plist;          // [*nprim] primary slots in cell order
   const long long* nprim;    // device scalar: number of primaries
+  int* spill;                // per-wave lists of a shell's secondaries (multi-chunk bases)
+  int spill_cap;             // entries per wave (0: no spill lists, search per chunk)
   int* queue;                // device scalar: next primary (relative to p_begin)
   unsigned long long* pairs; // device scalar: accepted pairs
   long long p_begin;         // first primary of this pair-block
@@ -125,15 +130,19 @@ struct ZetaArgs {
   const long long* nprim;
   long long row_begin;       // global primary index of A row 0
   long long sub_begin;       // first row of this sub-block (relative to A)
-  int K;                     // rows in this sub-block (upper bound)
+  long long K;               // rows in this sub-block (upper bound)
   RowLayout lay;
   void* ops;                 // bf16 split operands
-  float* C32;                // [splitK][sum W_m^2] partial Gram (FP32 / BF16X3)
-  double* C64;               // [splitK][sum W_m^2] partial Gram (FP64)
+  float* C32;                // partial Gram products (FP32 / BF16X3)
+  double* C64;               // partial Gram products (FP64)
   double* zeta;
   int prec;
 };
-hipError_t launch_zeta_block(const ZetaArgs& z, hipStream_t st);
+// Every block of kZetaBlock primaries of a pair-block: z.sub_begin = 0 and
+// z.K = rows of the pair-block.
+hipError_t launch_zeta_pairblock(const ZetaArgs& z, hipStream_t st);
+// Doubles of the partial-Gram buffer (per-block partials of a pair-block).
+size_t zeta_partial_doubles(const RowLayout& L);
 
 // Adjoint helpers
 struct AdjArgs {

@@ -235,24 +235,34 @@ struct CartChunk {
     });
   }
 
-  // adjoint: sum over this chunk's monomials of g_t * monomial (Horner in x)
+  // adjoint: sum over this chunk's monomials of g_t * monomial.  Powers of x
+  // and y are formed first so that every coefficient enters as a multiplicand
+  // (a scalar-register operand when the coefficients are uniform).
   template <typename GetG>
   static __device__ __forceinline__ Real poly(Real x, Real y, Real z, GetG&& g) {
+    Real xp[kDeg + 1], yp[kDeg + 1];
+    xp[0] = Real(1);
+    yp[0] = Real(1);
+#pragma unroll
+    for (int k = 1; k <= kDeg; ++k) {
+      xp[k] = xp[k - 1] * x;
+      yp[k] = yp[k - 1] * y;
+    }
     Real total = Real(0);
     Real zq = Real(1);
     static_for<kDeg + 1>([&](auto qc) {
       constexpr int q = decltype(qc)::value;
       if constexpr (q > 0) zq = zq * z;
       if constexpr (((QMASK >> q) & 1u) != 0) {
-        Real ysum = Real(0);  // sum_p y^p * (sum_k g x^k), Horner in y
-        static_for<kDeg + 1 - q>([&](auto pr) {
-          constexpr int p = kDeg - q - decltype(pr)::value;
-          Real hx = Real(0);
-          static_for<kDeg + 1 - q - p>([&](auto kr) {
-            constexpr int k = kDeg - q - p - decltype(kr)::value;
-            hx = fma_r(hx, x, g(cart_index_c(k, p, q)));
+        Real ysum = Real(0);
+        static_for<kDeg + 1 - q>([&](auto pc) {
+          constexpr int p = decltype(pc)::value;
+          Real hx = g(cart_index_c(0, p, q));
+          static_for<kDeg - q - p>([&](auto kc) {
+            constexpr int k = decltype(kc)::value + 1;
+            hx = fma_r(g(cart_index_c(k, p, q)), xp[k], hx);
           });
-          ysum = fma_r(ysum, y, hx);
+          ysum = fma_r(hx, yp[p], ysum);
         });
         total = fma_r(ysum, zq, total);
       }
@@ -348,9 +358,15 @@ struct SpinChunk {
     }
   }
 
-  // adjoint: sum over this chunk of g_t * Re/Im parts of (x - i y)^m z^n
+  // adjoint: sum over this chunk of g_t * Re/Im parts of (x - i y)^m z^n,
+  // with the powers of z formed first so that every coefficient enters as a
+  // multiplicand (a scalar-register operand when the coefficients are uniform).
   template <typename GetG>
   static __device__ __forceinline__ Real poly(Real x, Real y, Real z, GetG&& g) {
+    Real zn[kDeg + 1];
+    zn[0] = Real(1);
+#pragma unroll
+    for (int n = 1; n <= kDeg; ++n) zn[n] = zn[n - 1] * z;
     Real total = Real(0);
     Real cr = Real(1), ci = Real(0);
     static_for<M1 + 1>([&](auto mc) {
@@ -362,12 +378,13 @@ struct SpinChunk {
         ci = ni;
       }
       if constexpr (m >= M0) {
-        // Horner in z over n for the Re and Im coefficient sets
-        Real hr = Real(0), hi = Real(0);
-        static_for<kDeg - m + 1>([&](auto nr_) {
-          constexpr int n = kDeg - m - decltype(nr_)::value;
-          hr = fma_r(hr, z, g(spin_index_c(m, n, 0)));
-          if constexpr (m > 0) hi = fma_r(hi, z, g(spin_index_c(m, n, 1)));
+        Real hr = g(spin_index_c(m, 0, 0));
+        Real hi = Real(0);
+        if constexpr (m > 0) hi = g(spin_index_c(m, 0, 1));
+        static_for<kDeg - m>([&](auto nc) {
+          constexpr int n = decltype(nc)::value + 1;
+          hr = fma_r(g(spin_index_c(m, n, 0)), zn[n], hr);
+          if constexpr (m > 0) hi = fma_r(g(spin_index_c(m, n, 1)), zn[n], hi);
         });
         if constexpr (m == 0)
           total += hr;

@@ -83,16 +83,15 @@ struct RunEntry<double> {
 };
 
 // ---------------------------------------------------------------- per-wave LDS
-// M holds the shell's reduced monomial sums (forward) or, in the adjoint, the
-// FP64 polynomial coefficients g_t of the shell.
+// M holds the shell's reduced monomial sums (forward only).
 template <typename Real, bool ADJ>
 struct WaveLds {
   using V = typename V4<Real>::T;
-  using MT = std::conditional_t<ADJ, double, Real>;
   int pre[kMaxRuns];           // first virtual candidate index of each run
   RunEntry<Real> run[kMaxRuns];
-  V ring[kRing];               // (u_x, u_y, u_z, w) forward; (u_x, u_y, u_z, index) adjoint
-  MT M[kTermsCart + 1];        // (+1 padding slot)
+  V ring[kRing];               // (d_x, d_y, d_z, w) forward; (d_x, d_y, d_z, index) adjoint
+  int ring_j[kRing];           // secondary index of a ring entry (when spilled)
+  Real M[ADJ ? 1 : kTermsCart + 1];  // (+1 padding slot)
 };
 
 __device__ __forceinline__ void wave_lds_fence() {
@@ -198,8 +197,10 @@ struct Occ {
       ADJOINT ? 3 : ((std::is_same<Real, float>::value && BASIS == G3PCF_BASIS_SPIN) ? 3 : 2);
 };
 
-template <bool B>
-using bool_c = std::integral_constant<bool, B>;
+template <class... C>
+constexpr int n_chunks(ChunkList<C...>) {
+  return int(sizeof...(C));
+}
 
 // ---------------------------------------------------------------- the kernel
 template <typename Real, int BASIS, bool ADJOINT>
@@ -207,6 +208,9 @@ struct PairKernel {
   using V = typename V4<Real>::T;
   using Lds = WaveLds<Real, ADJOINT>;
   static constexpr bool kF32 = std::is_same<Real, float>::value;
+  static constexpr int kTerms = (BASIS == G3PCF_BASIS_SPIN) ? kTermsSpin : kTermsCart;
+  // read-only device memory in the constant address space (scalar loads)
+  using CoefPtr = const double __attribute__((address_space(4)))*;
 
   // Per-primary state shared by the shell searches.
   struct Primary {
@@ -404,10 +408,11 @@ struct PairKernel {
 
   // One search of shell b over the annulus [r0, r1): every accepted pair is
   // appended to the LDS ring as (separation, weight or index), and every full
-  // wave of pairs is handed to consume(entry, valid) (one pair per lane); the
+  // wave of pairs is handed to consume(entry, index, valid) (one pair per
+  // lane; the index only with SPILL); the
   // remainder at the end.  The position loads of the next window are issued
   // before the current window is binned.
-  template <bool MINIMG, typename Consume>
+  template <bool MINIMG, bool SPILL, typename Consume>
   static __device__ __forceinline__ unsigned search_shell(const PairArgs& a, Lds& W,
                                                           const V* __restrict__ pos4,
                                                           const Primary& P, int b, double r0,
@@ -479,7 +484,9 @@ struct PairKernel {
           } else {
             ent.w = q.w;
           }
-          W.ring[(head + cnt + lanes_below(m)) & (kRing - 1)] = ent;
+          const int slot = (head + cnt + lanes_below(m)) & (kRing - 1);
+          W.ring[slot] = ent;
+          if constexpr (SPILL) W.ring_j[slot] = j;
         }
         const int got = __popcll(m);
         cnt += got;
@@ -487,7 +494,8 @@ struct PairKernel {
         if (cnt >= kWave) {
           wave_lds_fence();
           const V ent = W.ring[(head + lane) & (kRing - 1)];
-          consume(ent, true);
+          const int jj = SPILL ? W.ring_j[(head + lane) & (kRing - 1)] : 0;
+          consume(ent, jj, true);
           head = (head + kWave) & (kRing - 1);
           cnt -= kWave;
         }
@@ -513,42 +521,124 @@ struct PairKernel {
     if (cnt > 0) {
       wave_lds_fence();
       V ent;
+      int jj = 0;
       if (lane < cnt) {
         ent = W.ring[(head + lane) & (kRing - 1)];
+        if constexpr (SPILL) jj = W.ring_j[(head + lane) & (kRing - 1)];
       } else {
         ent.x = Real(0);
         ent.y = Real(0);
         ent.z = Real(1);
         ent.w = ADJOINT ? pack_index(0, Real(0)) : Real(0);
       }
-      consume(ent, lane < cnt);
+      consume(ent, jj, lane < cnt);
       wave_lds_fence();
     }
     return accepted;
   }
 
+  // Separation of secondary j from the primary exactly as the search forms
+  // it (same reference point or minimum image, same rounding).
+  template <bool MINIMG>
+  static __device__ __forceinline__ void separation(const PairArgs& a, const Primary& P,
+                                                    const V& q, Real d[3]) {
+    if constexpr (kF32) {
+      float ref[3] = {P.pref[0], P.pref[1], P.pref[2]};
+      if (!MINIMG && a.periodic) {
+        // the run's image shift: the unique k with |q - p + k L| < L / 2
+        const double qq[3] = {double(q.x), double(q.y), double(q.z)};
+        for (int c = 0; c < 3; ++c) {
+          const double k = -rint((qq[c] - P.p[c]) / a.L[c]);
+          ref[c] = float(P.p[c] - k * a.L[c]);
+        }
+      }
+      float dx = __fsub_rn(q.x, ref[0]), dy = __fsub_rn(q.y, ref[1]), dz = __fsub_rn(q.z, ref[2]);
+      if constexpr (MINIMG) {
+        dx = fma_r(-P.L[0], __builtin_rintf(__fmul_rn(dx, P.invL[0])), dx);
+        dy = fma_r(-P.L[1], __builtin_rintf(__fmul_rn(dy, P.invL[1])), dy);
+        dz = fma_r(-P.L[2], __builtin_rintf(__fmul_rn(dz, P.invL[2])), dz);
+      }
+      d[0] = dx;
+      d[1] = dy;
+      d[2] = dz;
+    } else {
+      double r2;
+      P.bin64.classify(q, P.p, d, r2);
+    }
+  }
+
+  // Stream `count` spilled secondaries of a shell (one per lane, the next
+  // wave's loads in flight) into body(unit vector, weight).
+  template <bool ROT, bool MINIMG, typename Body>
+  static __device__ __forceinline__ void replay(const PairArgs& a, const V* __restrict__ pos4,
+                                                const Primary& P, const int* __restrict__ sp,
+                                                int count, Body&& body) {
+    const int lane = threadIdx.x % kWave;
+    const int last = count - 1;
+    int jn = sp[min(lane, last)];
+    V qn = pos4[jn];
+    for (int base = 0; base < count; base += kWave) {
+      const V q = qn;
+      const bool valid = base + lane < count;
+      jn = sp[min(base + kWave + lane, last)];
+      qn = pos4[jn];
+      V e;
+      Real d[3];
+      separation<MINIMG>(a, P, q, d);
+      e.x = valid ? d[0] : Real(0);
+      e.y = valid ? d[1] : Real(0);
+      e.z = valid ? d[2] : Real(1);
+      Real ux, uy, uz;
+      unit<ROT>(P, e, ux, uy, uz);
+      body(ux, uy, uz, valid ? q.w : Real(0));
+    }
+  }
+
   // All chunks (forward) or the adjoint of shell b, with the line-of-sight
-  // rotation and the minimum-image mode fixed at compile time.
+  // rotation and the minimum-image mode fixed at compile time.  With several
+  // chunks, the first search also writes the shell's secondaries to the
+  // wave's spill list, and the later chunks replay it instead of searching
+  // again (unless it overflowed).
   template <bool ROT, bool MINIMG>
   static __device__ __forceinline__ unsigned shell(const PairArgs& a, Lds& W,
                                                    const V* __restrict__ pos4, const Primary& P,
                                                    int b, double r0, double r1, long long row,
-                                                   double w_prim) {
+                                                   double w_prim, int* __restrict__ sp) {
+    const int lane = threadIdx.x % kWave;
     unsigned got = 0;
     if constexpr (!ADJOINT) {
       using CL = typename Chunks<Real, BASIS>::type;
+      constexpr bool kMulti = n_chunks(CL{}) > 1;
+      const int cap = a.spill_cap;
       bool first = true;
+      bool replayable = false;
       for_each_chunk(CL{}, [&](auto* tag) {
         using Chunk = std::remove_pointer_t<decltype(tag)>;
         Chunk ch;
         ch.zero();
-        const unsigned g = search_shell<MINIMG>(a, W, pos4, P, b, r0, r1,
-                                                [&](const V& e, bool) {
-                                                  Real ux, uy, uz;
-                                                  unit<ROT>(P, e, ux, uy, uz);
-                                                  ch.add(ux, uy, uz, e.w);
-                                                });
-        if (first) got = g;
+        auto add = [&](const V& e) {
+          Real ux, uy, uz;
+          unit<ROT>(P, e, ux, uy, uz);
+          ch.add(ux, uy, uz, e.w);
+        };
+        if (first && kMulti && cap > 0) {
+          int nsp = 0;
+          got = search_shell<MINIMG, true>(a, W, pos4, P, b, r0, r1,
+                                           [&](const V& e, int j, bool valid) {
+                                             if (valid && nsp + lane < cap) sp[nsp + lane] = j;
+                                             nsp += __popcll(__ballot(valid));
+                                             add(e);
+                                           });
+          replayable = got <= unsigned(cap);
+        } else if (!first && replayable) {
+          replay<ROT, MINIMG>(a, pos4, P, sp, int(got), [&](Real ux, Real uy, Real uz, Real w) {
+            ch.add(ux, uy, uz, w);
+          });
+        } else {
+          const unsigned g = search_shell<MINIMG, false>(a, W, pos4, P, b, r0, r1,
+                                                         [&](const V& e, int, bool) { add(e); });
+          if (first) got = g;
+        }
         first = false;
         reduce_store(W, ch);
       });
@@ -556,12 +646,15 @@ struct PairKernel {
       convert(a, W, b, row);
       wave_lds_fence();
     } else {
-      load_gcoef(a, W, b, row);
-      got = search_shell<MINIMG>(a, W, pos4, P, b, r0, r1, [&](const V& e, bool valid) {
-        Real ux, uy, uz;
-        unit<ROT>(P, e, ux, uy, uz);
-        scatter_one(a, W, ux, uy, uz, unpack_index(e.w), valid, w_prim);
-      });
+      // the shell's coefficients, read through the scalar cache (uniform)
+      const CoefPtr gc = (CoefPtr)(a.gcoef + (row * a.nbins + b) * kTerms);
+      got = search_shell<MINIMG, false>(a, W, pos4, P, b, r0, r1,
+                                        [&](const V& e, int, bool valid) {
+                                          Real ux, uy, uz;
+                                          unit<ROT>(P, e, ux, uy, uz);
+                                          scatter_one(a, gc, ux, uy, uz, unpack_index(e.w), valid,
+                                                      w_prim);
+                                        });
       wave_lds_fence();
     }
     return got;
@@ -578,6 +671,8 @@ struct PairKernel {
     const long long NP = min(a.p_count, (long long)(*a.nprim) - a.p_begin);
     const int nb = a.nbins;
     const double margin = a.rmax_search - a.rmax;
+    // this wave's spill list (multi-chunk bases)
+    int* sp = a.spill + size_t(blockIdx.x * kWavesPerBlock + wid) * size_t(a.spill_cap);
     unsigned long long my_pairs = 0;
 
     while (true) {
@@ -616,14 +711,14 @@ struct PairKernel {
         const double r1 = (b + 1 == nb) ? a.rmax_search : (b + 1) * a.rmax / nb + margin;
         if (P.rotate) {
           if (kF32 && P.minimg)
-            my_pairs += shell<true, kF32>(a, W, pos4, P, b, r0, r1, row, w_prim);
+            my_pairs += shell<true, kF32>(a, W, pos4, P, b, r0, r1, row, w_prim, sp);
           else
-            my_pairs += shell<true, false>(a, W, pos4, P, b, r0, r1, row, w_prim);
+            my_pairs += shell<true, false>(a, W, pos4, P, b, r0, r1, row, w_prim, sp);
         } else {
           if (kF32 && P.minimg)
-            my_pairs += shell<false, kF32>(a, W, pos4, P, b, r0, r1, row, w_prim);
+            my_pairs += shell<false, kF32>(a, W, pos4, P, b, r0, r1, row, w_prim, sp);
           else
-            my_pairs += shell<false, false>(a, W, pos4, P, b, r0, r1, row, w_prim);
+            my_pairs += shell<false, false>(a, W, pos4, P, b, r0, r1, row, w_prim, sp);
         }
       }
     }
@@ -708,28 +803,15 @@ struct PairKernel {
     }
   }
 
-  static __device__ __forceinline__ void load_gcoef(const PairArgs& a, Lds& W, int b,
-                                                    long long row) {
-    const int lane = threadIdx.x % kWave;
-    constexpr int T = (BASIS == G3PCF_BASIS_SPIN) ? kTermsSpin : kTermsCart;
-    const double* g = a.gcoef + (row * a.nbins + b) * T;
-    for (int t = lane; t < T; t += kWave) W.M[t] = g[t];
-    wave_lds_fence();
-  }
-
   // Adjoint for one pair per lane: the full polynomial sum_t g_t mono_t(u) in
-  // FP64 (its coefficients cancel strongly at l = 10), with the coefficients
-  // read from LDS through an offset the compiler cannot hoist out of the
-  // loop, so they do not occupy registers.
-  static __device__ __forceinline__ void scatter_one(const PairArgs& a, const Lds& W, Real ux,
+  // FP64 (its coefficients cancel strongly at l = 10).  The coefficients are
+  // the same for every lane, so they are read into scalar registers.
+  static __device__ __forceinline__ void scatter_one(const PairArgs& a, CoefPtr gc, Real ux,
                                                      Real uy, Real uz, int j, bool valid,
                                                      double w_prim) {
     using Poly = std::conditional_t<BASIS == G3PCF_BASIS_SPIN, SpinChunk<double, 0, kDeg>,
                                     CartChunk<double, (1u << (kDeg + 1)) - 1>>;
-    int off = 0;
-    asm volatile("" : "+v"(off));
-    const double v =
-        Poly::poly(double(ux), double(uy), double(uz), [&](int t) { return W.M[t + off]; });
+    const double v = Poly::poly(double(ux), double(uy), double(uz), [&](int t) { return gc[t]; });
     if (valid) unsafeAtomicAdd(&a.grad_w[j], w_prim * v);
   }
 };

@@ -7,9 +7,12 @@
 // contribution is a Gram product on the matrix cores:
 //   B_m = [Re A^m | Im A^m]  (K x W_m),   C_m = (diag(w) B_m)^T B_m,
 //   Re zeta^m = C_pp + C_qq,   Im zeta^m = C_qp - C_pq.
-// For m = 0 every a_l0 is real and B_0 = Re A^0.  Each block's C_m is added
-// into zeta in FP64.
+// For m = 0 every a_l0 is real and B_0 = Re A^0.  The blocks' C_m (FP32 or
+// FP64 accumulation on the matrix cores) are added into zeta in FP64, in
+// block order.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "internal.h"
 
@@ -70,65 +73,240 @@ __device__ __forceinline__ long long valid_rows(const ZetaArgs& z) {
   return kv < 0 ? 0 : kv;
 }
 
-// One wave per (m, 16x16 tile, K slice).  A operand = (w B_m)^T, B operand = B_m.
-// Lane l holds A[i = l % 16][k = l / 16] and B[k = l / 16][j = l % 16]; the
-// FP32 16x16 result sits in lanes as C[4 (l / 16) + r][l % 16], r = 0..3.
+// ---- FP32 / FP64: one workgroup per (m, 64 x 64 macro tile of C_m on or
+// above the diagonal, block of 4096 primaries).  Each step stages 32 rows of
+// the two column ranges in LDS (weights applied to the left operand, FP64 rows
+// converted to the working precision on the way), and each wave accumulates a
+// 32 x 32 quadrant as 2 x 2 MFMA tiles over the block's rows.  The next step's
+// rows are loaded into registers while the current step is multiplied.  In
+// FP32 the MFMA accumulators are added into FP64 ones every 512 rows, so the
+// block's partial is FP64 like the sum across blocks.
+constexpr int kMT = 64;     // macro tile
+constexpr int kKS = 32;     // rows per step
+constexpr int kFlush = 512; // rows per FP32 accumulation before the FP64 sum
+
+struct MDims {
+  int nm;
+  int W[kDeg + 1];
+  int off[kDeg + 1];
+  int cw[kDeg + 2];       // offsets of each C_m in a partial
+  int mt[kDeg + 2];       // cumulative macro tiles on or above the diagonal
+  int csize;
+};
+
+MDims make_mdims(const RowLayout& L) {
+  MDims d{};
+  d.nm = L.lmax + 1;
+  int cw = 0, mt = 0;
+  for (int m = 0; m < d.nm; ++m) {
+    d.W[m] = L.wm[m];
+    d.off[m] = L.off[m];
+    d.cw[m] = cw;
+    d.mt[m] = mt;
+    cw += L.wm[m] * L.wm[m];
+    const int t = (L.wm[m] + kMT - 1) / kMT;
+    mt += t * (t + 1) / 2;
+  }
+  d.cw[d.nm] = cw;
+  d.mt[d.nm] = mt;
+  d.csize = cw;
+  return d;
+}
+
+__device__ __forceinline__ void macro_tile_of(const MDims& d, int t, int& m, int& ti, int& tj) {
+  m = 0;
+  while (m + 1 < d.nm && t >= d.mt[m + 1]) ++m;
+  int r = t - d.mt[m];
+  const int nt = (d.W[m] + kMT - 1) / kMT;
+  ti = 0;
+  while (r >= nt - ti) {
+    r -= nt - ti;
+    ++ti;
+  }
+  tj = ti + r;
+}
+
 template <typename Real>
-__global__ __launch_bounds__(256) void k_gram_direct(ZetaArgs z, Dims d) {
-  const int wave = blockIdx.x * 4 + threadIdx.x / kWave;
-  const int lane = threadIdx.x % kWave;
-  const int ntile = d.tiles[d.nm];
-  if (wave >= ntile * kZetaSplitK) return;
-  const int s = wave / ntile;
+struct MfmaAcc;
+template <>
+struct MfmaAcc<float> {
+  using T = float4_t;
+  static __device__ __forceinline__ T mma(float a, float b, T c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // row of register r of lane group g in the 16 x 16 result
+  static __device__ __forceinline__ int row(int g, int r) { return 4 * g + r; }
+};
+template <>
+struct MfmaAcc<double> {
+  using T = double4_t;
+  static __device__ __forceinline__ T mma(double a, double b, T c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // the FP64 16x16x4 result interleaves rows (measured on gfx950)
+  static __device__ __forceinline__ int row(int g, int r) { return g + 4 * r; }
+};
+
+template <typename Real>
+__global__ __launch_bounds__(256) void k_gram_mt(ZetaArgs z, MDims d, double* __restrict__ Cpart) {
+  constexpr int kPad = (sizeof(Real) == 4) ? 16 : 8;  // row stride off the bank period
+  __shared__ Real Xs[2][kKS][kMT + kPad];
+  __shared__ Real Ys[2][kKS][kMT + kPad];
+  using Acc = MfmaAcc<Real>;
+  using AT = typename Acc::T;
+
+  const int tid = threadIdx.x;
+  const int lane = tid % kWave, wv = tid / kWave;
+  const int s = blockIdx.y;
   int m, ti, tj;
-  tile_of(d, wave % ntile, m, ti, tj);
-  const long long Kv = valid_rows(z);
+  macro_tile_of(d, blockIdx.x, m, ti, tj);
   const int W = d.W[m];
-  const int i = ti * kTile + lane % 16, j = tj * kTile + lane % 16;
-  const int g = lane / 16;
-  const long long per = ((Kv + 4 * kZetaSplitK - 1) / (4 * kZetaSplitK)) * 4;
-  const long long k0 = s * per, k1 = min(Kv, k0 + per);
-  const double* A = z.A + (z.sub_begin) * (long long)d.rowW + d.off[m];
-  const int* plist = z.plist + z.row_begin + z.sub_begin;
-  if constexpr (sizeof(Real) == 4) {
-    float4_t acc = {0.f, 0.f, 0.f, 0.f};
-    for (long long k = k0; k < k1; k += 4) {
-      const long long r = k + g;
-      float av = 0.f, bv = 0.f;
-      if (r < k1) {
-        const double wr = z.wsort[plist[r]];
-        const double* row = A + r * d.rowW;
-        if (i < W) av = float(wr * row[i]);
-        if (j < W) bv = float(row[j]);
+  const bool diag = (ti == tj);
+  const long long Kv = valid_rows(z);
+  const long long r0 = (long long)s * kZetaBlock;
+  const long long r1 = min(Kv, r0 + kZetaBlock);
+  const double* A = z.A + d.off[m];
+  const int* plist = z.plist + z.row_begin;
+
+  // staging: thread -> (row srow, 8 columns from scol) of both column ranges
+  const int srow = tid / 8, scol = (tid % 8) * 8;
+  const int ci0 = ti * kMT + scol, cj0 = tj * kMT + scol;
+  double xr[8], yr[8], wr = 0.0;
+  auto load = [&](long long kb) {
+    const long long r = kb + srow;
+    const bool ok = r < r1;
+    wr = ok ? z.wsort[plist[r]] : 0.0;
+    const double* row = A + (ok ? r : r0) * (long long)z.lay.W;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      xr[c] = (ok && ci0 + c < W) ? row[ci0 + c] : 0.0;
+      if (!diag) yr[c] = (ok && cj0 + c < W) ? row[cj0 + c] : 0.0;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      Xs[buf][srow][scol + c] = Real(wr * xr[c]);
+      Ys[buf][srow][scol + c] = Real(diag ? xr[c] : yr[c]);
+    }
+  };
+
+  AT acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = AT{0, 0, 0, 0};
+  const int qi = (wv >> 1) * 32, qj = (wv & 1) * 32;
+  const int li = lane % 16, g = lane / 16;
+
+  // FP32 accumulation runs over kFlush rows at a time and is then added into
+  // FP64 accumulators (the FP64 form accumulates in FP64 throughout)
+  double4_t tot[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) tot[a][b] = double4_t{0.0, 0.0, 0.0, 0.0};
+  auto flush = [&]() {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          tot[a][b][r] += double(acc[a][b][r]);
+          acc[a][b][r] = Real(0);
+        }
+  };
+
+  int buf = 0;
+  if (r0 < r1) {
+    load(r0);
+    store(0);
+  }
+  __syncthreads();
+  for (long long kb = r0; kb < r1; kb += kKS) {
+    const bool more = kb + kKS < r1;
+    if constexpr (sizeof(Real) == 4) {
+      if (kb > r0 && (kb - r0) % kFlush == 0) flush();
+    }
+    if (more) load(kb + kKS);
+#pragma unroll
+    for (int k = 0; k < kKS; k += 4) {
+      const int kk = k + g;
+      Real xa[2], yb[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) xa[a] = Xs[buf][kk][qi + a * 16 + li];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) yb[b] = Ys[buf][kk][qj + b * 16 + li];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = Acc::mma(xa[a], yb[b], acc[a][b]);
+    }
+    if (more) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+
+  flush();
+  double* C = Cpart + (long long)s * d.csize + d.cw[m];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = ti * kMT + qi + a * 16 + Acc::row(g, r);
+        const int j = tj * kMT + qj + b * 16 + li;
+        if (i < W && j < W) C[i * W + j] = tot[a][b][r];
       }
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+}
+
+// zeta[m][l][l'][b1][b2] += sum over the pair-block's 4096-primary blocks (in
+// order, FP64) of the block Gram products.  Only macro tiles on or above the
+// diagonal are stored; C_m is symmetric.
+template <typename CT>
+__global__ void k_zeta_accum_mt(const CT* __restrict__ C, int nsub, MDims d, RowLayout L,
+                                double* __restrict__ zeta) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int nb = L.nb, nm = L.lmax + 1;
+  const long long per_m = (long long)nm * nm * nb * nb;
+  if (idx >= per_m * nm) return;
+  long long t = idx;
+  const int b2 = int(t % nb); t /= nb;
+  const int b1 = int(t % nb); t /= nb;
+  const int lp = int(t % nm); t /= nm;
+  const int l = int(t % nm); t /= nm;
+  const int m = int(t);
+  if (l < m || lp < m) return;
+  const int W = d.W[m];
+  auto at = [&](int i, int j) {
+    if (i / kMT > j / kMT) {
+      const int x = i;
+      i = j;
+      j = x;
     }
-    float* C = z.C32 + (long long)s * d.csize + d.cw[m];
-    for (int r = 0; r < 4; ++r) {
-      const int ii = ti * kTile + 4 * g + r;
-      if (ii < W && j < W) C[ii * W + j] = acc[r];
-    }
-  } else {
-    double4_t acc = {0.0, 0.0, 0.0, 0.0};
-    for (long long k = k0; k < k1; k += 4) {
-      const long long r = k + g;
-      double av = 0.0, bv = 0.0;
-      if (r < k1) {
-        const double wr = z.wsort[plist[r]];
-        const double* row = A + r * d.rowW;
-        if (i < W) av = wr * row[i];
-        if (j < W) bv = row[j];
-      }
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-    }
-    // The FP64 16x16x4 result interleaves rows: lane group g, register r
-    // holds row g + 4 r (measured on gfx950; the FP32 form holds 4 g + r).
-    double* C = z.C64 + (long long)s * d.csize + d.cw[m];
-    for (int r = 0; r < 4; ++r) {
-      const int ii = ti * kTile + g + 4 * r;
-      if (ii < W && j < W) C[ii * W + j] = acc[r];
+    return d.cw[m] + i * W + j;
+  };
+  const int P = (l - m) * nb + b1, Pp = (lp - m) * nb + b2;
+  const int dm = L.d[m];
+  const int Q = dm + P, Qp = dm + Pp;
+  const int iPP = at(P, Pp);
+  const int iQQ = (m > 0) ? at(Q, Qp) : 0, iQP = (m > 0) ? at(Q, Pp) : 0,
+            iPQ = (m > 0) ? at(P, Qp) : 0;
+  double re = 0.0, im = 0.0;
+  for (int s = 0; s < nsub; ++s) {
+    const CT* c = C + (long long)s * d.csize;
+    if (m == 0) {
+      re += double(c[iPP]);
+    } else {
+      re += double(c[iPP]) + double(c[iQQ]);
+      im += double(c[iQP]) - double(c[iPQ]);
     }
   }
+  double* o = zeta + idx * 2;
+  o[0] += re;
+  o[1] += im;
 }
 
 // ---- BF16x3: x = x0 + x1 + x2 with each xk the round-to-nearest-even bfloat16
@@ -266,32 +444,50 @@ RowLayout make_layout(int lmax, int nb) {
   return L;
 }
 
-hipError_t launch_zeta_block(const ZetaArgs& z, hipStream_t st) {
-  const Dims d = make_dims(z.lay);
-  const int waves = d.tiles[d.nm] * kZetaSplitK;
-  const unsigned blocks = unsigned((waves + 3) / 4);
+size_t zeta_partial_doubles(const RowLayout& L) {
+  const int nsub_max = (kPairBlockMax + kZetaBlock - 1) / kZetaBlock;
+  return size_t(std::max(nsub_max, kZetaSplitK)) * size_t(sum_wm2(L));
+}
+
+// All blocks of 4096 primaries of a pair-block (z.sub_begin = 0, z.K = rows).
+hipError_t launch_zeta_pairblock(const ZetaArgs& z, hipStream_t st) {
   if (z.prec == G3PCF_PREC_BF16X3) {
-    const int Kp = ((z.K + 31) / 32) * 32;
-    const long long total = (long long)d.rowW * Kp;
-    hipLaunchKernelGGL(k_split_bf16, dim3(unsigned((total + 255) / 256)), dim3(256), 0, st, z, d,
-                       Kp);
-    hipLaunchKernelGGL(k_gram_bf16x3, dim3(blocks), dim3(256), 0, st, z, d, Kp);
-  } else if (z.prec == G3PCF_PREC_FP32) {
-    hipLaunchKernelGGL((k_gram_direct<float>), dim3(blocks), dim3(256), 0, st, z, d);
-  } else {
-    hipLaunchKernelGGL((k_gram_direct<double>), dim3(blocks), dim3(256), 0, st, z, d);
+    for (long long s0 = 0; s0 < z.K; s0 += kZetaBlock) {
+      ZetaArgs b = z;
+      b.sub_begin = s0;
+      b.K = int(std::min<long long>(kZetaBlock, z.K - s0));
+      const Dims d = make_dims(b.lay);
+      const int waves = d.tiles[d.nm] * kZetaSplitK;
+      const unsigned blocks = unsigned((waves + 3) / 4);
+      const int Kp = ((b.K + 31) / 32) * 32;
+      const long long total = (long long)d.rowW * Kp;
+      hipLaunchKernelGGL(k_split_bf16, dim3(unsigned((total + 255) / 256)), dim3(256), 0, st, b,
+                         d, Kp);
+      hipLaunchKernelGGL(k_gram_bf16x3, dim3(blocks), dim3(256), 0, st, b, d, Kp);
+      const long long entries = (long long)(b.lay.lmax + 1) * (b.lay.lmax + 1) *
+                                (b.lay.lmax + 1) * b.lay.nb * b.lay.nb;
+      hipLaunchKernelGGL((k_zeta_accum<float>), dim3(unsigned((entries + 255) / 256)), dim3(256),
+                         0, st, b.C32, d, b.lay, b.zeta);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
   }
+  const MDims d = make_mdims(z.lay);
+  const int nsub = int((z.K + kZetaBlock - 1) / kZetaBlock);
+  if (nsub <= 0) return hipSuccess;
+  const dim3 grid(unsigned(d.mt[d.nm]), unsigned(nsub));
+  if (z.prec == G3PCF_PREC_FP32)
+    hipLaunchKernelGGL((k_gram_mt<float>), grid, dim3(256), 0, st, z, d, z.C64);
+  else
+    hipLaunchKernelGGL((k_gram_mt<double>), grid, dim3(256), 0, st, z, d, z.C64);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const long long entries = (long long)(z.lay.lmax + 1) * (z.lay.lmax + 1) * (z.lay.lmax + 1) *
                             z.lay.nb * z.lay.nb;
   const unsigned ab = unsigned((entries + 255) / 256);
-  if (z.prec == G3PCF_PREC_FP64)
-    hipLaunchKernelGGL((k_zeta_accum<double>), dim3(ab), dim3(256), 0, st, z.C64, d, z.lay,
-                       z.zeta);
-  else
-    hipLaunchKernelGGL((k_zeta_accum<float>), dim3(ab), dim3(256), 0, st, z.C32, d, z.lay,
-                       z.zeta);
+  hipLaunchKernelGGL((k_zeta_accum_mt<double>), dim3(ab), dim3(256), 0, st, z.C64, nsub, d,
+                     z.lay, z.zeta);
   return hipGetLastError();
 }
 
