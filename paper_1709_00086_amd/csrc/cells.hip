@@ -245,10 +245,10 @@ Grid make_grid(const g3pcf_problem& p) {
   for (int a = 0; a < 3; ++a)
     ext = std::max(ext, std::fabs(p.box_lo[a]) + std::fabs(p.box[a]));
   g.rsearch = p.rmax * (1.0 + 1e-5) + 1e-6 * ext + 1e-9;
-  // Cells of about R_max / 8 across the rows and R_max / 16 along x: a row
+  // Cells of about R_max / 8 across the rows and R_max / 64 along x: a row
   // (cy, cz) of cells is a contiguous run of galaxies, and the x-interval of
   // an annulus in a row is cut to within one thin cell at each end.
-  const double target[3] = {p.rmax / 16.0, p.rmax / 8.0, p.rmax / 8.0};
+  const double target[3] = {p.rmax / 64.0, p.rmax / 8.0, p.rmax / 8.0};
   int64_t cap = std::max<int64_t>(64, 4 * p.n);
   cap = std::min<int64_t>(cap, int64_t(1) << 24);
   for (int a = 0; a < 3; ++a) {
