@@ -146,9 +146,25 @@ __device__ __forceinline__ void axis_range(double p, int c_u, int nc, double lo,
   dmax = fmax(fabs(a - p), fabs(b - p));
 }
 
-__device__ __forceinline__ int floor_div(int a, int b) {
-  int q = a / b;
-  if ((a % b != 0) && ((a < 0) != (b < 0))) --q;
+// Periodic wrap of an unwrapped cell index c in [-n, 2n) (a search window on a
+// non-tight axis spans less than one box): c -> c - k n with k in {-1, 0, 1}.
+__device__ __forceinline__ int wrap_cell(int c, int n, int& k) {
+  k = (c < 0) ? -1 : (c >= n ? 1 : 0);
+  return c - k * n;
+}
+
+// q = r / d and r - q d for 0 <= r < 2^24 and a uniform d > 0, from a float
+// reciprocal corrected by one step.
+__device__ __forceinline__ int div_small(int r, int d, float inv_d, int& rem) {
+  int q = int(float(r) * inv_d);
+  rem = r - q * d;
+  if (rem < 0) {
+    --q;
+    rem += d;
+  } else if (rem >= d) {
+    ++q;
+    rem -= d;
+  }
   return q;
 }
 
@@ -228,8 +244,8 @@ struct PairKernel {
   // `total` to their summed length.
   static __device__ __forceinline__ int build_runs(const PairArgs& a, const int* __restrict__ cs,
                                                    const Primary& P, double r0, double r1,
-                                                   const int c0[3], int nyr, int rb, int nrows,
-                                                   Lds& W, int& total) {
+                                                   const int c0[3], int nyr, float inv_nyr,
+                                                   int rb, int nrows, Lds& W, int& total) {
     const int lane = threadIdx.x % kWave;
     const double* p = P.p;
     const int nx = a.nc[0], ny = a.nc[1], nz = a.nc[2];
@@ -238,21 +254,16 @@ struct PairKernel {
     int ky = 0, kz = 0;
     const int r = rb + lane;
     if (r < nrows) {
-      const int czu = c0[2] + r / nyr, cyu = c0[1] + r % nyr;
+      int ry;
+      const int czu = c0[2] + div_small(r, nyr, inv_nyr, ry), cyu = c0[1] + ry;
       double dzmin, dzmax, dymin, dymax;
       axis_range(p[2], czu, nz, a.lo[2], a.s[2], a.periodic, a.tight[2], a.L[2], dzmin, dzmax);
       axis_range(p[1], cyu, ny, a.lo[1], a.s[1], a.periodic, a.tight[1], a.L[1], dymin, dymax);
       const double d2min = dymin * dymin + dzmin * dzmin;
       if (d2min < r1 * r1) {
         int cz = czu, cy = cyu;
-        if (a.periodic && !a.tight[2]) {
-          kz = floor_div(czu, nz);
-          cz = czu - kz * nz;
-        }
-        if (a.periodic && !a.tight[1]) {
-          ky = floor_div(cyu, ny);
-          cy = cyu - ky * ny;
-        }
+        if (a.periodic && !a.tight[2]) cz = wrap_cell(czu, nz, kz);
+        if (a.periodic && !a.tight[1]) cy = wrap_cell(cyu, ny, ky);
         const int row = (cz * ny + cy) * nx;
         // up to two x-intervals of cells (unwrapped indices)
         int ia[2] = {0, 0}, ib[2] = {0, 0}, ni = 0;
@@ -261,10 +272,15 @@ struct PairKernel {
           ib[0] = nx - 1;
           ni = 1;
         } else {
-          const double hx1 = sqrt(r1 * r1 - d2min);
+          // FP32 square roots, widened by a relative 2e-6: far inside the
+          // search margin that the annulus radii already carry
+          const double hx1 =
+              double(__builtin_sqrtf(float(r1 * r1 - d2min))) * (1.0 + 2e-6) + 1e-6;
           const double d2max = dymax * dymax + dzmax * dzmax;
           const bool cut = r0 > 0.0 && !a.tight[1] && !a.tight[2] && r0 * r0 > d2max;
-          const double hx0 = cut ? sqrt(r0 * r0 - d2max) : 0.0;
+          const double hx0 =
+              cut ? fmax(0.0, double(__builtin_sqrtf(float(r0 * r0 - d2max))) * (1.0 - 2e-6) - 1e-6)
+                  : 0.0;
           int a1 = cell_floor(p[0] - hx1, a.lo[0], a.inv_s[0]);
           int b1 = cell_floor(p[0] - hx0, a.lo[0], a.inv_s[0]);
           int a2 = cell_floor(p[0] + hx0, a.lo[0], a.inv_s[0]);
@@ -291,8 +307,8 @@ struct PairKernel {
         int ca[4] = {0, 0, 0, 0}, cb[4] = {0, 0, 0, 0}, kk[4] = {0, 0, 0, 0}, nr = 0;
         for (int i = 0; i < ni; ++i) {
           if (a.periodic && !a.tight[0]) {
-            const int k0 = floor_div(ia[i], nx);
-            const int lo_c = ia[i] - k0 * nx, hi_c = ib[i] - k0 * nx;
+            int k0;
+            const int lo_c = wrap_cell(ia[i], nx, k0), hi_c = ib[i] - k0 * nx;
             if (hi_c < nx) {
               ca[nr] = lo_c;
               cb[nr] = hi_c;
@@ -436,6 +452,7 @@ struct PairKernel {
     }
     const int nyr = c1[1] - c0[1] + 1, nzr = c1[2] - c0[2] + 1;
     const int nrows = nyr * nzr;
+    const float inv_nyr = 1.0f / float(nyr);
     float lo2 = 0.0f, hi2 = 0.0f;
     if constexpr (kF32) {
       lo2 = a.r2_lo[b];
@@ -445,7 +462,7 @@ struct PairKernel {
     unsigned accepted = 0;
     for (int rb = 0; rb < nrows; rb += kWave) {
       int total = 0;
-      const int nrun = build_runs(a, cs, P, r0, r1, c0, nyr, rb, nrows, W, total);
+      const int nrun = build_runs(a, cs, P, r0, r1, c0, nyr, inv_nyr, rb, nrows, W, total);
       if (total == 0) continue;
       int kb = 0;
       // bin one window and append its accepted pairs to the ring; consume a
@@ -766,7 +783,10 @@ struct PairKernel {
   static __device__ __forceinline__ void reduce_store(Lds& W, Chunk& ch) {
     constexpr int NT = Chunk::NT;
     constexpr int kJunk = kTermsCart;  // slot that absorbs padding in the last group
-    const int row = (threadIdx.x % kWave) >> 4;
+    const int lane = threadIdx.x % kWave;
+    const int row = lane >> 4;
+    const bool ge1 = row >= 1, ge2 = row >= 2, ge3 = row >= 3;
+    const bool leader = (lane & 15) == 0;  // one store per row
     static_for<(NT + 3) / 4>([&](auto gc) {
       constexpr int g = decltype(gc)::value;
       constexpr int i0 = 4 * g, i1 = 4 * g + 1, i2 = 4 * g + 2, i3 = 4 * g + 3;
@@ -780,8 +800,16 @@ struct PairKernel {
       constexpr int te = (i1 < NT) ? Chunk::term_of(i1) : kJunk;
       constexpr int tb = (i2 < NT) ? Chunk::term_of(i2) : kJunk;
       constexpr int tf = (i3 < NT) ? Chunk::term_of(i3) : kJunk;
-      const int t = row == 0 ? ta : (row == 1 ? te : (row == 2 ? tb : tf));
-      W.M[t] = tot;
+      int t;
+      if constexpr (te == ta + 1 && tb == ta + 2 && tf == ta + 3) {
+        t = ta + row;
+      } else {
+        t = ta;
+        t = ge1 ? te : t;
+        t = ge2 ? tb : t;
+        t = ge3 ? tf : t;
+      }
+      if (leader) W.M[t] = tot;
     });
   }
 
