@@ -80,8 +80,8 @@ struct PairArgs {
   const int* cell_start;     // [ncell + 1]
   const int* plist;          // [*nprim] primary slots in cell order
   const long long* nprim;    // device scalar: number of primaries
-  int* spill;                // per-wave lists of a shell's secondaries (multi-chunk bases)
-  int spill_cap;             // entries per wave (0: no spill lists, search per chunk)
+  int* spill;                // per-wave lists of a shell's secondaries
+  int spill_cap;             // entries per wave (0: no spill lists: one search per shell and chunk)
   int* queue;                // device scalar: next primary (relative to p_begin)
   unsigned long long* pairs; // device scalar: accepted pairs
   long long p_begin;         // first primary of this pair-block

@@ -232,6 +232,7 @@ struct PairKernel {
   struct Primary {
     double p[3];
     Real pref[3];  // primary position in the working precision
+    double invLd[3];
     Real L[3], invL[3];
     Real Rm[9];    // line-of-sight rotation
     bool rotate;
@@ -564,8 +565,10 @@ struct PairKernel {
       if (!MINIMG && a.periodic) {
         // the run's image shift: the unique k with |q - p + k L| < L / 2
         const double qq[3] = {double(q.x), double(q.y), double(q.z)};
+        // |q - p + k L| stays far from L / 2 on a non-tight axis, so the
+        // product with 1/L rounds to the same k as the quotient would
         for (int c = 0; c < 3; ++c) {
-          const double k = -rint((qq[c] - P.p[c]) / a.L[c]);
+          const double k = -rint((qq[c] - P.p[c]) * P.invLd[c]);
           ref[c] = float(P.p[c] - k * a.L[c]);
         }
       }
@@ -584,31 +587,53 @@ struct PairKernel {
     }
   }
 
-  // Stream `count` spilled secondaries of a shell (one per lane, the next
-  // wave's loads in flight) into body(unit vector, weight).
+  // Stream `count` spilled secondaries of a shell, one per lane, into
+  // body(unit vector, weight, index, valid).  Two batches alternate so that
+  // the next batch's gathers and the batch after that's indices are in flight
+  // while one batch is used.
   template <bool ROT, bool MINIMG, typename Body>
-  static __device__ __forceinline__ void replay(const PairArgs& a, const V* __restrict__ pos4,
-                                                const Primary& P, const int* __restrict__ sp,
-                                                int count, Body&& body) {
+  static __device__ __forceinline__ void replay_all(const PairArgs& a,
+                                                    const V* __restrict__ pos4,
+                                                    const Primary& P, const int* __restrict__ sp,
+                                                    int count, Body&& body) {
+    if (count <= 0) return;
     const int lane = threadIdx.x % kWave;
     const int last = count - 1;
-    int jn = sp[min(lane, last)];
-    V qn = pos4[jn];
-    for (int base = 0; base < count; base += kWave) {
-      const V q = qn;
+    auto use = [&](const V& q, int j, int base) {
       const bool valid = base + lane < count;
-      jn = sp[min(base + kWave + lane, last)];
-      qn = pos4[jn];
-      V e;
       Real d[3];
       separation<MINIMG>(a, P, q, d);
+      V e;
       e.x = valid ? d[0] : Real(0);
       e.y = valid ? d[1] : Real(0);
       e.z = valid ? d[2] : Real(1);
       Real ux, uy, uz;
       unit<ROT>(P, e, ux, uy, uz);
-      body(ux, uy, uz, valid ? q.w : Real(0));
+      body(ux, uy, uz, valid ? q.w : Real(0), j, valid);
+    };
+    int ja = sp[min(lane, last)];
+    int jb = sp[min(kWave + lane, last)];
+    V qa = pos4[ja];
+    for (int base = 0; base < count; base += 2 * kWave) {
+      const V qb = pos4[jb];
+      const int jn = sp[min(base + 2 * kWave + lane, last)];
+      use(qa, ja, base);
+      ja = jn;
+      qa = pos4[ja];
+      const int jbb = jb;
+      jb = sp[min(base + 3 * kWave + lane, last)];
+      use(qb, jbb, base + kWave);
     }
+  }
+
+  template <bool ROT, bool MINIMG, typename Body>
+  static __device__ __forceinline__ void replay(const PairArgs& a, const V* __restrict__ pos4,
+                                                const Primary& P, const int* __restrict__ sp,
+                                                int count, Body&& body) {
+    replay_all<ROT, MINIMG>(a, pos4, P, sp, count,
+                            [&](Real ux, Real uy, Real uz, Real w, int, bool) {
+                              body(ux, uy, uz, w);
+                            });
   }
 
   // All chunks (forward) or the adjoint of shell b, with the line-of-sight
@@ -708,6 +733,7 @@ struct PairKernel {
         P.L[c] = Real(a.L[c]);
         P.invL[c] = Real(1.0 / a.L[c]);
         P.pref[c] = Real(P.p[c]);
+        P.invLd[c] = 1.0 / a.L[c];
         P.bin64.L[c] = a.L[c];
       }
       // FP64 always measures from the primary with the minimum image (the
