@@ -36,6 +36,9 @@ struct V4<double> {
 };
 
 __device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uniform_real(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
 
 __device__ __forceinline__ double uniform_double(double v) {
   const long long b = __double_as_longlong(v);
@@ -44,6 +47,7 @@ __device__ __forceinline__ double uniform_double(double v) {
   return __longlong_as_double((static_cast<long long>(hi) << 32) |
                               (static_cast<unsigned int>(lo)));
 }
+__device__ __forceinline__ double uniform_real(double v) { return uniform_double(v); }
 
 // DPP move with compile-time controls (old value 0 where the row is masked).
 // With bound_ctrl set and full masks the compiler folds the move into the add.

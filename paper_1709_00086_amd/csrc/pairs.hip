@@ -120,31 +120,37 @@ __device__ __forceinline__ int unpack_index(float v) { return __float_as_int(v);
 __device__ __forceinline__ int unpack_index(double v) { return int(v); }
 
 // ---------------------------------------------------------------- geometry
-// Distance range along one axis from p to cell c_u (unwrapped index): the
-// nearest and farthest points of the cell.  The outer cells of an open box
-// also hold any point beyond it, and on a tight periodic axis the nearest
-// distance is taken over the images (the farthest is then not used).
-__device__ __forceinline__ void axis_range(double p, int c_u, int nc, double lo, double s,
-                                           int periodic, int tight, double L, double& dmin,
-                                           double& dmax) {
-  if (tight) {
-    double best = 1e300;
+// Distance range along one axis from the primary to cell c_u (unwrapped
+// index): the nearest and farthest points of the cell.  The outer cells of an
+// open box also hold any point beyond it, and on a tight periodic axis the
+// nearest distance is taken over the images (the farthest is then not used).
+// Computed in cell units measured from the primary: prel is the primary's
+// coordinate in cells ((p - lo) / s, FP64), the result in length units (FP32).  The rounding (about 1e-6 cells) is far inside the search
+// margin, which enters the squared distances as 2 R_max * margin.
+__device__ __forceinline__ void axis_range_f(double prel, int c_u, int nc, float s,
+                                             int periodic, int tight, float& dmin,
+                                             float& dmax) {
+  const float t0 = float(double(c_u) - prel);
+  if (tight) {  // min over the images of wrapped cell c_u
+    float best = __builtin_huge_valf();
     for (int k = -1; k <= 1; ++k) {
-      const double a = lo + c_u * s + k * L, b = a + s;
-      best = fmin(best, fmax(0.0, fmax(a - p, p - b)));
+      const float lo = t0 + float(k * nc), hi = lo + 1.0f;
+      best = fminf(best, fmaxf(0.0f, fmaxf(lo, -hi)));
     }
-    dmin = best;
-    dmax = 1e300;
+    dmin = best * s;
+    dmax = __builtin_huge_valf();
     return;
   }
-  double a = lo + c_u * s, b = a + s;
-  if (!periodic) {
-    if (c_u == 0) a = -1e300;
-    if (c_u == nc - 1) b = 1e300;
+  float lo = t0, hi = t0 + 1.0f;
+  if (!periodic) {  // the outer cells also hold any point beyond the box
+    if (c_u == 0) lo = -__builtin_huge_valf();
+    if (c_u == nc - 1) hi = __builtin_huge_valf();
   }
-  dmin = fmax(0.0, fmax(a - p, p - b));
-  dmax = fmax(fabs(a - p), fabs(b - p));
+  dmin = fmaxf(0.0f, fmaxf(lo, -hi)) * s;
+  dmax = fmaxf(fabsf(lo), fabsf(hi)) * s;
 }
+
+__device__ __forceinline__ int cell_of(double c) { return int(fmin(fmax(floor(c), -1e9), 1e9)); }
 
 // Periodic wrap of an unwrapped cell index c in [-n, 2n) (a search window on a
 // non-tight axis spans less than one box): c -> c - k n with k in {-1, 0, 1}.
@@ -233,6 +239,8 @@ struct PairKernel {
     double p[3];
     Real pref[3];  // primary position in the working precision
     double invLd[3];
+    double prel[3];  // primary position in cell units, (p - lo) / s
+    float sf[3];     // cell sides
     Real L[3], invL[3];
     Real Rm[9];    // line-of-sight rotation
     bool rotate;
@@ -257,11 +265,11 @@ struct PairKernel {
     if (r < nrows) {
       int ry;
       const int czu = c0[2] + div_small(r, nyr, inv_nyr, ry), cyu = c0[1] + ry;
-      double dzmin, dzmax, dymin, dymax;
-      axis_range(p[2], czu, nz, a.lo[2], a.s[2], a.periodic, a.tight[2], a.L[2], dzmin, dzmax);
-      axis_range(p[1], cyu, ny, a.lo[1], a.s[1], a.periodic, a.tight[1], a.L[1], dymin, dymax);
-      const double d2min = dymin * dymin + dzmin * dzmin;
-      if (d2min < r1 * r1) {
+      float dzmin, dzmax, dymin, dymax;
+      axis_range_f(P.prel[2], czu, nz, P.sf[2], a.periodic, a.tight[2], dzmin, dzmax);
+      axis_range_f(P.prel[1], cyu, ny, P.sf[1], a.periodic, a.tight[1], dymin, dymax);
+      const float d2min = dymin * dymin + dzmin * dzmin;
+      if (double(d2min) < r1 * r1) {
         int cz = czu, cy = cyu;
         if (a.periodic && !a.tight[2]) cz = wrap_cell(czu, nz, kz);
         if (a.periodic && !a.tight[1]) cy = wrap_cell(cyu, ny, ky);
@@ -273,19 +281,20 @@ struct PairKernel {
           ib[0] = nx - 1;
           ni = 1;
         } else {
-          // FP32 square roots, widened by a relative 2e-6: far inside the
-          // search margin that the annulus radii already carry
-          const double hx1 =
-              double(__builtin_sqrtf(float(r1 * r1 - d2min))) * (1.0 + 2e-6) + 1e-6;
-          const double d2max = dymax * dymax + dzmax * dzmax;
-          const bool cut = r0 > 0.0 && !a.tight[1] && !a.tight[2] && r0 * r0 > d2max;
-          const double hx0 =
-              cut ? fmax(0.0, double(__builtin_sqrtf(float(r0 * r0 - d2max))) * (1.0 - 2e-6) - 1e-6)
-                  : 0.0;
-          int a1 = cell_floor(p[0] - hx1, a.lo[0], a.inv_s[0]);
-          int b1 = cell_floor(p[0] - hx0, a.lo[0], a.inv_s[0]);
-          int a2 = cell_floor(p[0] + hx0, a.lo[0], a.inv_s[0]);
-          int b2 = cell_floor(p[0] + hx1, a.lo[0], a.inv_s[0]);
+          // half-chords in FP32, widened by a relative 2e-6 (inside the margin)
+          const float hx1 =
+              __builtin_sqrtf(float(r1 * r1 - double(d2min))) * (1.0f + 2e-6f) + 1e-6f;
+          const float d2max = dymax * dymax + dzmax * dzmax;
+          const bool cut = r0 > 0.0 && !a.tight[1] && !a.tight[2] && r0 * r0 > double(d2max);
+          const float hx0 =
+              cut ? fmaxf(0.0f, __builtin_sqrtf(float(r0 * r0 - double(d2max))) * (1.0f - 2e-6f) -
+                                    1e-6f)
+                  : 0.0f;
+          const double px = P.prel[0], ix = a.inv_s[0];
+          int a1 = cell_of(px - double(hx1) * ix);
+          int b1 = cell_of(px - double(hx0) * ix);
+          int a2 = cell_of(px + double(hx0) * ix);
+          int b2 = cell_of(px + double(hx1) * ix);
           if (!a.periodic) {
             a1 = min(max(a1, 0), nx - 1);
             b1 = min(max(b1, 0), nx - 1);
@@ -729,11 +738,15 @@ struct PairKernel {
       P.p[1] = uniform_double(double(pv.y));
       P.p[2] = uniform_double(double(pv.z));
       frame(a, P);
+      // uniform per primary: held in scalar registers
+      for (int i = 0; i < 9; ++i) P.Rm[i] = uniform_real(P.Rm[i]);
       for (int c = 0; c < 3; ++c) {
-        P.L[c] = Real(a.L[c]);
-        P.invL[c] = Real(1.0 / a.L[c]);
-        P.pref[c] = Real(P.p[c]);
+        P.L[c] = uniform_real(Real(a.L[c]));
+        P.invL[c] = uniform_real(Real(1.0 / a.L[c]));
+        P.pref[c] = uniform_real(Real(P.p[c]));
         P.invLd[c] = 1.0 / a.L[c];
+        P.prel[c] = uniform_double((P.p[c] - a.lo[c]) * a.inv_s[c]);
+        P.sf[c] = uniform_real(float(a.s[c]));
         P.bin64.L[c] = a.L[c];
       }
       // FP64 always measures from the primary with the minimum image (the
