@@ -57,6 +57,7 @@ int hip_fail(hipError_t e, const char* where) {
 }
 
 constexpr size_t kAlign = 256;
+constexpr size_t kCountersBytes = 1024;
 size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Ws {
@@ -99,7 +100,7 @@ Ws plan(const g3pcf_problem& p, int backward) {
   w.flags = take(size_t(2 * (n + 1)) * 4);
   w.plist = take(size_t(n) * 4);
   w.scan = take(w.scan_bytes);
-  w.counters = take(256);
+  w.counters = take(kCountersBytes);
   // per-wave spill lists for bases accumulated in several register chunks
   const bool multi = fp64 || p.basis == G3PCF_BASIS_CARTESIAN;
   w.spill = take(multi ? size_t(kPairWaves) * kSpillCap * 4 : 0);
@@ -181,8 +182,10 @@ struct Counters {
   long long nprim;
   unsigned long long pairs;
   unsigned long long pairs_adj;
-  int queue;
+  int pad[10];
+  int queue[kQueues * kQueueStride];  // one primary counter per XCD, 64 B apart
 };
+static_assert(sizeof(Counters) <= kCountersBytes, "counters block");
 
 // Stages shared by forward and backward: cell list and primary list.
 int stage_catalogue(const g3pcf_problem& p, const Ws& w, void* ws, hipStream_t st) {
@@ -211,7 +214,7 @@ PairArgs pair_args(const g3pcf_problem& p, const Ws& w, void* ws) {
   a.nprim = &c->nprim;
   a.spill = at<int>(ws, w.spill);
   a.spill_cap = w.spill_cap;
-  a.queue = &c->queue;
+  a.queue = c->queue;
   a.pairs = &c->pairs;
   for (int k = 0; k < 3; ++k) {
     a.nc[k] = w.grid.nc[k];

@@ -24,6 +24,10 @@ constexpr int kOutPerBin = (kDeg + 1) * (kDeg + 1);  // real a_lm outputs per sh
 constexpr int kZetaBlock = 4096;
 // Split-K slices of the Gram product (partials summed in order in FP64).
 constexpr int kZetaSplitK = 4;
+// Primary queues of the pair kernel: one per XCD (workgroups are dispatched to
+// the 8 XCDs round-robin), each counter on its own 64-byte line.
+constexpr int kQueues = 8;
+constexpr int kQueueStride = 16;
 // Persistent waves of the pair kernel.
 constexpr int kPairWaves = 4096;
 // Spill-list entries per wave: a shell's secondaries kept for the later
@@ -82,7 +86,7 @@ struct PairArgs {
   const long long* nprim;    // device scalar: number of primaries
   int* spill;                // per-wave lists of a shell's secondaries
   int spill_cap;             // entries per wave (0: no spill lists: one search per shell and chunk)
-  int* queue;                // device scalar: next primary (relative to p_begin)
+  int* queue;                // kQueues counters (stride kQueueStride): next primary of each XCD's share
   unsigned long long* pairs; // device scalar: accepted pairs
   long long p_begin;         // first primary of this pair-block
   long long p_count;         // primaries in this pair-block (upper bound)

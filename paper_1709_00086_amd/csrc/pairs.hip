@@ -726,11 +726,30 @@ struct PairKernel {
     int* sp = a.spill + size_t(blockIdx.x * kWavesPerBlock + wid) * size_t(a.spill_cap);
     unsigned long long my_pairs = 0;
 
+    // The pair-block's primaries (in cell order) are split into kQueues
+    // contiguous shares, one per XCD: a wave takes primaries from its own XCD's
+    // share first, so the candidates of the primaries an XCD works on at once
+    // are neighbours in its L2, then helps the other shares.
+    const int xcc = int(blockIdx.x % kQueues);
+    const long long share = (NP + kQueues - 1) / kQueues;
+    int qx = 0;  // shares visited
     while (true) {
-      int qi = 0;
-      if (lane == 0) qi = atomicAdd(a.queue, 1);
-      qi = uniform_int(__shfl(qi, 0));
-      if (qi >= NP) break;
+      long long qi = 0;
+      bool found = false;
+      while (qx < kQueues) {
+        const int x = (xcc + qx) % kQueues;
+        const long long lo = x * share, hi = min(NP, lo + share);
+        int t = 0;
+        if (lane == 0) t = atomicAdd(a.queue + x * kQueueStride, 1);
+        t = uniform_int(__shfl(t, 0));
+        if (lo + t < hi) {
+          qi = lo + t;
+          found = true;
+          break;
+        }
+        ++qx;
+      }
+      if (!found) break;
       const int slot = uniform_int(a.plist[a.p_begin + qi]);
       const V pv = pos4[slot];
       Primary P;
@@ -890,11 +909,13 @@ __global__ __launch_bounds__(kWave* kWavesPerBlock)
   PairKernel<Real, BASIS, ADJOINT>::run(a);
 }
 
-__global__ void k_zero_queue(int* q) { *q = 0; }
+__global__ void k_zero_queue(int* q) {
+  if (threadIdx.x < kQueues) q[threadIdx.x * kQueueStride] = 0;
+}
 
 template <typename Real, int BASIS, bool ADJOINT>
 hipError_t launch_one(const PairArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(k_zero_queue, dim3(1), dim3(1), 0, st, a.queue);
+  hipLaunchKernelGGL(k_zero_queue, dim3(1), dim3(kWave), 0, st, a.queue);
   const long long want = (a.p_count + kWavesPerBlock - 1) / kWavesPerBlock;
   const unsigned blocks = unsigned(std::min<long long>(want, kPairWaves / kWavesPerBlock));
   const size_t lds = sizeof(typename PairKernel<Real, BASIS, ADJOINT>::Lds) * kWavesPerBlock;
