@@ -261,12 +261,20 @@ struct CartChunk {
         Real ysum = Real(0);
         static_for<kDeg + 1 - q>([&](auto pc) {
           constexpr int p = decltype(pc)::value;
-          Real hx = g(cart_index_c(0, p, q));
-          static_for<kDeg - q - p>([&](auto kc) {
-            constexpr int k = decltype(kc)::value + 1;
-            hx = fma_r(g(cart_index_c(k, p, q)), xp[k], hx);
-          });
-          ysum = fma_r(hx, yp[p], ysum);
+          constexpr int KM = kDeg - q - p;  // highest power of x
+          if constexpr (KM == 0) {
+            ysum = fma_r(g(cart_index_c(0, p, q)), yp[p], ysum);
+          } else {
+            // start from a product and add the constant term last, so that no
+            // coefficient has to be copied into a vector register first
+            Real hx = g(cart_index_c(1, p, q)) * xp[1];
+            static_for<KM - 1>([&](auto kc) {
+              constexpr int k = decltype(kc)::value + 2;
+              hx = fma_r(g(cart_index_c(k, p, q)), xp[k], hx);
+            });
+            hx = hx + g(cart_index_c(0, p, q));
+            ysum = fma_r(hx, yp[p], ysum);
+          }
         });
         total = fma_r(ysum, zq, total);
       }
@@ -382,18 +390,31 @@ struct SpinChunk {
         ci = ni;
       }
       if constexpr (m >= M0) {
-        Real hr = g(spin_index_c(m, 0, 0));
-        Real hi = Real(0);
-        if constexpr (m > 0) hi = g(spin_index_c(m, 0, 1));
-        static_for<kDeg - m>([&](auto nc) {
-          constexpr int n = decltype(nc)::value + 1;
-          hr = fma_r(g(spin_index_c(m, n, 0)), zn[n], hr);
-          if constexpr (m > 0) hi = fma_r(g(spin_index_c(m, n, 1)), zn[n], hi);
-        });
-        if constexpr (m == 0)
-          total += hr;
-        else
-          total = fma_r(cr, hr, fma_r(ci, hi, total));
+        constexpr int NM = kDeg - m;  // highest power of z
+        if constexpr (NM == 0) {
+          // m = kDeg: only the constant coefficients
+          if constexpr (m == 0)
+            total += g(spin_index_c(m, 0, 0));
+          else
+            total = fma_r(cr, g(spin_index_c(m, 0, 0)), fma_r(ci, g(spin_index_c(m, 0, 1)), total));
+        } else {
+          // start from a product and add the constant term last, so that no
+          // coefficient has to be copied into a vector register first
+          Real hr = g(spin_index_c(m, 1, 0)) * zn[1];
+          Real hi = Real(0);
+          if constexpr (m > 0) hi = g(spin_index_c(m, 1, 1)) * zn[1];
+          static_for<NM - 1>([&](auto nc) {
+            constexpr int n = decltype(nc)::value + 2;
+            hr = fma_r(g(spin_index_c(m, n, 0)), zn[n], hr);
+            if constexpr (m > 0) hi = fma_r(g(spin_index_c(m, n, 1)), zn[n], hi);
+          });
+          hr = hr + g(spin_index_c(m, 0, 0));
+          if constexpr (m > 0) hi = hi + g(spin_index_c(m, 0, 1));
+          if constexpr (m == 0)
+            total += hr;
+          else
+            total = fma_r(cr, hr, fma_r(ci, hi, total));
+        }
       }
     });
     return total;
