@@ -196,3 +196,29 @@ def test_repeatable(dev):
         z1, _ = run_gpu(cat, dev, prec, "cartesian")
         z2, _ = run_gpu(cat, dev, prec, "cartesian")
         assert np.array_equal(z1, z2), prec
+
+
+@functools.lru_cache(maxsize=None)
+def _dense_case():
+    # ~23k pairs per primary in two shells: the outer shell holds more
+    # secondaries than a wave's spill list (16,384), the inner one fewer, so the
+    # multi-chunk bases take both the replay path and the repeated-search path
+    cat = C.tiny(n=60000, L=100.0, seed=21, rmax=45.0, nbins=2, lmax=10, periodic=True,
+                 los="z", dtype=np.float32)
+    mask = C.primary_mask(cat.pos.shape[0], 256, seed=22)
+    ref, pairs = oracle.zeta(cat, primary_mask=mask, return_pairs=True)
+    return cat, mask, ref, pairs
+
+
+@pytest.mark.parametrize("precision,basis", [("fp64", "cartesian"), ("fp64", "spin"),
+                                             ("fp32", "cartesian"), ("fp32", "spin")])
+def test_dense_shells_beyond_spill_capacity(dev, precision, basis):
+    say(f"case dense two-shell catalogue {precision} {basis}")
+    cat, mask, ref, pairs_ref = _dense_case()
+    assert pairs_ref > 256 * 16384  # the outer shell overflows a spill list
+    z, pairs = run_gpu(cat, dev, precision, basis, mask=mask)
+    compare(z, ref, 1e-10 if precision == "fp64" else 1e-5, f"dense {precision} {basis}")
+    if precision == "fp64":
+        assert pairs == pairs_ref
+    else:
+        assert abs(pairs - pairs_ref) <= 2 + 1e-6 * pairs_ref
