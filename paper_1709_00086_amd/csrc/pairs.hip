@@ -4,8 +4,10 @@
 //
 // One wavefront owns one primary at a time and pulls primaries from a shared
 // counter (dynamic scheduling over primaries, as the paper's OpenMP dynamic
-// schedule).  For its primary the wave takes the radial shells one after the
-// other; for shell b it
+// schedule; one counter per XCD over a contiguous share of the primaries, so
+// that the primaries an XCD works on at once share candidates in its L2).
+// For its primary the wave takes the radial shells one after the other; for
+// shell b it
 //   1. builds, 64 rows of cells at a time (one lane per (cy, cz) row), the
 //      runs of galaxies that can lie in the annulus: per row the x-interval
 //      of the outer sphere minus the x-interval of the inner sphere, i.e. at
@@ -13,18 +15,20 @@
 //      periodic box).  All cell-start lookups of the 64 rows are in flight at
 //      once, and the runs go into a table in LDS with their prefix sums;
 //   2. streams the runs' galaxies with one candidate per lane (a lane finds
-//      its run from the prefix sums), bins each candidate, and appends the
-//      accepted ones, already rotated and normalised, to a ring of pairs in
-//      LDS -- the GPU form of the paper's per-bin pair buckets;
-//   3. whenever the ring holds a full wave of pairs, accumulates them, one
-//      pair per lane, into every monomial sum of the shell held in registers
-//      (vectorised over pairs, not over monomials, as in the paper's
-//      vectorisation section);
+//      its run from the prefix sums; the next window's loads are in flight
+//      while one is binned), bins each candidate, and appends the accepted
+//      separations to a ring of pairs in LDS -- the GPU form of the paper's
+//      per-bin pair buckets;
+//   3. whenever the ring holds a full wave of pairs, normalises and rotates
+//      them and accumulates them, one pair per lane, into every monomial sum
+//      of the shell held in registers (vectorised over pairs, not over
+//      monomials, as in the paper's vectorisation section);
 //   4. reduces the per-lane partials once per (primary, shell) with DPP and
 //      converts the shell's monomial sums to a_lm in FP64.
 // No neighbour list ever leaves the compute unit.  A basis whose sums do not
-// fit in registers at once is accumulated in chunks, each with its own
-// search of the shell.
+// fit in registers at once is accumulated in chunks: the first chunk's
+// search also writes the shell's secondary indices to the wave's spill list,
+// which the later chunks replay (a repeated search if the list overflowed).
 //
 // The adjoint kernel runs the same search and, per accepted pair, evaluates
 // the shell's adjoint polynomial and adds it to the secondary's gradient.
