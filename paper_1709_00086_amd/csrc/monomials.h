@@ -35,15 +35,22 @@ struct V4<double> {
   using T = double4;
 };
 
-__device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+// Copies of a wave-uniform value in scalar registers.  The value passes
+// through an empty asm statement first: the compiler drops readfirstlane of a
+// value it already knows to be uniform, and such values then stay in (and
+// spill from) vector registers.
+__device__ __forceinline__ int uniform_int(int v) {
+  asm("" : "+v"(v));
+  return __builtin_amdgcn_readfirstlane(v);
+}
 __device__ __forceinline__ float uniform_real(float v) {
-  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+  return __int_as_float(uniform_int(__float_as_int(v)));
 }
 
 __device__ __forceinline__ double uniform_double(double v) {
   const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readfirstlane(int(b & 0xffffffffll));
-  const int hi = __builtin_amdgcn_readfirstlane(int(b >> 32));
+  const int lo = uniform_int(int(b & 0xffffffffll));
+  const int hi = uniform_int(int(b >> 32));
   return __longlong_as_double((static_cast<long long>(hi) << 32) |
                               (static_cast<unsigned int>(lo)));
 }

@@ -103,6 +103,15 @@ __device__ __forceinline__ void wave_lds_fence() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// Lane index computed in place (the compiler cannot hoist an asm statement),
+// so that no lane-dependent address has to stay live, or be spilled, across
+// the accumulation loops.
+__device__ __forceinline__ int lane_here() {
+  int v;
+  asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(v));
+  return v;
+}
+
 __device__ __forceinline__ int lanes_below(unsigned long long m) {
   return __builtin_amdgcn_mbcnt_hi(unsigned(m >> 32), __builtin_amdgcn_mbcnt_lo(unsigned(m), 0));
 }
@@ -253,10 +262,10 @@ struct PairKernel {
   };
 
   // Runs of the rows [rb, rb + 64) of the window for the annulus
-  // r0 <= r < r1 into the LDS table; returns the number of runs and sets
-  // `total` to their summed length.
+  // r0 <= r < r1 (given as r0^2, r1^2) into the LDS table; returns the number
+  // of runs and sets `total` to their summed length.
   static __device__ __forceinline__ int build_runs(const PairArgs& a, const int* __restrict__ cs,
-                                                   const Primary& P, double r0, double r1,
+                                                   const Primary& P, double r0sq, double r1sq,
                                                    const int c0[3], int nyr, float inv_nyr,
                                                    int rb, int nrows, Lds& W, int& total) {
     const int lane = threadIdx.x % kWave;
@@ -273,7 +282,7 @@ struct PairKernel {
       axis_range_f(P.prel[2], czu, nz, P.sf[2], a.periodic, a.tight[2], dzmin, dzmax);
       axis_range_f(P.prel[1], cyu, ny, P.sf[1], a.periodic, a.tight[1], dymin, dymax);
       const float d2min = dymin * dymin + dzmin * dzmin;
-      if (double(d2min) < r1 * r1) {
+      if (double(d2min) < r1sq) {
         int cz = czu, cy = cyu;
         if (a.periodic && !a.tight[2]) cz = wrap_cell(czu, nz, kz);
         if (a.periodic && !a.tight[1]) cy = wrap_cell(cyu, ny, ky);
@@ -287,11 +296,11 @@ struct PairKernel {
         } else {
           // half-chords in FP32, widened by a relative 2e-6 (inside the margin)
           const float hx1 =
-              __builtin_sqrtf(float(r1 * r1 - double(d2min))) * (1.0f + 2e-6f) + 1e-6f;
+              __builtin_sqrtf(float(r1sq - double(d2min))) * (1.0f + 2e-6f) + 1e-6f;
           const float d2max = dymax * dymax + dzmax * dzmax;
-          const bool cut = r0 > 0.0 && !a.tight[1] && !a.tight[2] && r0 * r0 > double(d2max);
+          const bool cut = r0sq > 0.0 && !a.tight[1] && !a.tight[2] && r0sq > double(d2max);
           const float hx0 =
-              cut ? fmaxf(0.0f, __builtin_sqrtf(float(r0 * r0 - double(d2max))) * (1.0f - 2e-6f) -
+              cut ? fmaxf(0.0f, __builtin_sqrtf(float(r0sq - double(d2max))) * (1.0f - 2e-6f) -
                                     1e-6f)
                   : 0.0f;
           const double px = P.prel[0], ix = a.inv_s[0];
@@ -464,9 +473,12 @@ struct PairKernel {
         }
       }
     }
-    const int nyr = c1[1] - c0[1] + 1, nzr = c1[2] - c0[2] + 1;
+    // uniform per shell: kept in scalar registers across the window loops
+    for (int ax = 1; ax < 3; ++ax) c0[ax] = uniform_int(c0[ax]);
+    const int nyr = uniform_int(c1[1] - c0[1] + 1), nzr = uniform_int(c1[2] - c0[2] + 1);
     const int nrows = nyr * nzr;
-    const float inv_nyr = 1.0f / float(nyr);
+    const float inv_nyr = uniform_real(1.0f / float(nyr));
+    const double r0sq = uniform_double(r0 * r0), r1sq = uniform_double(r1 * r1);
     float lo2 = 0.0f, hi2 = 0.0f;
     if constexpr (kF32) {
       lo2 = a.r2_lo[b];
@@ -476,7 +488,7 @@ struct PairKernel {
     unsigned accepted = 0;
     for (int rb = 0; rb < nrows; rb += kWave) {
       int total = 0;
-      const int nrun = build_runs(a, cs, P, r0, r1, c0, nyr, inv_nyr, rb, nrows, W, total);
+      const int nrun = build_runs(a, cs, P, r0sq, r1sq, c0, nyr, inv_nyr, rb, nrows, W, total);
       if (total == 0) continue;
       int kb = 0;
       // bin one window and append its accepted pairs to the ring; consume a
@@ -786,8 +798,9 @@ struct PairKernel {
 
       for (int b = 0; b < nb; ++b) {
         // annulus of shell b, widened by the search margin on both sides
-        const double r0 = fmax(0.0, b * a.rmax / nb - margin);
-        const double r1 = (b + 1 == nb) ? a.rmax_search : (b + 1) * a.rmax / nb + margin;
+        const double r0 = uniform_double(fmax(0.0, b * a.rmax / nb - margin));
+        const double r1 =
+            uniform_double((b + 1 == nb) ? a.rmax_search : (b + 1) * a.rmax / nb + margin);
         if (P.rotate) {
           if (kF32 && P.minimg)
             my_pairs += shell<true, kF32>(a, W, pos4, P, b, r0, r1, row, w_prim, sp);
@@ -845,7 +858,7 @@ struct PairKernel {
   static __device__ __forceinline__ void reduce_store(Lds& W, Chunk& ch) {
     constexpr int NT = Chunk::NT;
     constexpr int kJunk = kTermsCart;  // slot that absorbs padding in the last group
-    const int lane = threadIdx.x % kWave;
+    const int lane = lane_here();
     const int row = lane >> 4;
     const bool ge1 = row >= 1, ge2 = row >= 2, ge3 = row >= 3;
     const bool leader = (lane & 15) == 0;  // one store per row
