@@ -79,7 +79,7 @@ def main():
                     help="time the forward pass only (not the contract's step)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
-    ap.add_argument("--sample", type=int, default=1024,
+    ap.add_argument("--sample", type=int, default=8192,
                     help="primaries in the seeded sample used for errors and the CPU baseline")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (reference for the "
