@@ -49,10 +49,11 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def measured_traffic(basis, precision, workload):
-    """HBM bytes per pair-kernel launch from the committed FETCH_SIZE /
-    WRITE_SIZE profile, or None if the kernel sources changed since then or
-    the profile does not cover this configuration."""
+def measured_profile(basis, precision, workload):
+    """The committed rocprofv3 counter record of the pair kernel (HBM bytes
+    from FETCH_SIZE / WRITE_SIZE, FP32 VALU instructions from the SQ
+    counters, per launch), or None if the kernel sources changed since then
+    or the profile does not cover this configuration."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "pair_kernel_uniform_n1048576_traffic.json")
     if not (os.path.exists(path) and basis == "spin" and precision != "fp64"
@@ -64,7 +65,7 @@ def measured_traffic(basis, precision, workload):
         h.update(open(os.path.join(ROOT, f), "rb").read())
     if h.hexdigest() != rec["source_sha256"]:
         return None
-    return rec["traffic_bytes_per_launch"]
+    return rec
 
 
 def main():
@@ -154,6 +155,7 @@ def main():
     achieved_tflops = pairs_per_launch * fpp / (avg_launch_ms * 1e-3) / 1e12
     peak = PEAK["fp64_vector_tflops"] if args.precision == "fp64" else PEAK["fp32_vector_tflops"]
     pair_kernel_pairs_per_s = pairs_per_launch / (avg_launch_ms * 1e-3)
+    prof = measured_profile(args.basis, args.precision, args.workload)
     value = pairs / (ms_per_step * 1e-3)
     log(f"step {ms_per_step:.1f} ms; stages (ms/step) {json.dumps(stage_ms)}")
     log(f"pair kernel: {len(pair_launches)} launches, avg {avg_launch_ms:.2f} ms, "
@@ -200,9 +202,15 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": achieved_tflops / peak,
-            "traffic": measured_traffic(args.basis, args.precision, args.workload),
+            "traffic": prof["traffic_bytes_per_launch"] if prof else None,
         },
     }
+    if prof and "valu_flops_per_launch" in prof:
+        # FP32 VALU flops the counters saw per launch (every instruction the
+        # kernel issues, not only the accumulation), over the live launch time
+        counted = prof["valu_flops_per_launch"] / (avg_launch_ms * 1e-3) / 1e12
+        out["pair_kernel"]["counted_valu_tflops"] = counted
+        out["pair_kernel"]["counted_frac_of_fp32_peak"] = counted / PEAK["fp32_vector_tflops"]
 
     # the same seeded primary sample for the errors, the FP64 speedup and the CPU baseline
     mask_np = C.primary_mask(cat.n, min(args.sample, cat.n), seed=7)

@@ -69,8 +69,9 @@ __global__ void k_build_mh(const double* __restrict__ gz, AdjDims d, double* __r
   const int W = d.W[m], dm = d.d[m], nb = d.nb;
   const int r = idx - d.cw[m];
   const int k = r / W, j = r % W;  // entry M_H[j][k]
+  const int nl = d.lmax + 1 - m;  // l values per shell in block m
   auto G = [&](int a, int b, int part) {  // G^m[a][b] over (l, b) indices
-    const int l = m + a / nb, b1 = a % nb, lp = m + b / nb, b2 = b % nb;
+    const int l = m + a % nl, b1 = a / nl, lp = m + b % nl, b2 = b / nl;
     return gz[zidx(d.lmax, nb, m, l, lp, b1, b2) + part];
   };
   double v;
@@ -223,10 +224,11 @@ __global__ __launch_bounds__(kFinThreads) void k_adj_finish(AdjArgs a, AdjDims d
         const int l = t.out_l[out];
         if (l > d.lmax) continue;
         const int m = t.out_m[out], part = t.out_part[out];
-        const int col = d.off[m] + (l - m) * nb + (part ? d.d[m] : 0);
+        const int nl = d.lmax + 1 - m;  // column stride between shells
+        const int col = d.off[m] + (l - m) + (part ? d.d[m] : 0);
         const double c = part ? -t.tcoef[e] : t.tcoef[e];
         for (int q = 0; q < kFinShells; ++q)
-          if (b0 + q < nb) sacc[q] += c * hs[col + b0 + q];
+          if (b0 + q < nb) sacc[q] += c * hs[col + (b0 + q) * nl];
       }
       for (int q = 0; q < kFinShells; ++q)
         if (b0 + q < nb) gout[(b0 + q) * T + term] = sacc[q];

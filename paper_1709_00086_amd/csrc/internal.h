@@ -67,13 +67,18 @@ struct Grid {
 
 Grid make_grid(const g3pcf_problem& p);
 
-// Layout of one shell's real outputs inside an A row.
+// Layout of the real outputs of a primary inside an A row: block m holds the
+// real parts, then (m >= 1) the imaginary parts, of a_lm(b) for l >= m; within
+// a half, shell-major (one shell's l values are adjacent, so the pair kernel
+// writes each shell's outputs as short contiguous runs).
 struct RowLayout {
   int lmax, nb;
   int W;               // total row width
   int off[kDeg + 2];   // column offset of each m block
   int d[kDeg + 1];     // (lmax + 1 - m) * nb
   int wm[kDeg + 1];    // block width: d for m = 0, 2d for m >= 1
+  // column of (l, shell b) within a half of block m
+  __host__ __device__ int pos(int m, int l, int b) const { return b * (lmax + 1 - m) + (l - m); }
 };
 
 RowLayout make_layout(int lmax, int nb);

@@ -910,7 +910,7 @@ struct PairKernel {
       double s = 0.0;
       for (int e = t.rowptr[o]; e < t.rowptr[o + 1]; ++e)
         s = __builtin_fma(t.coef[e], double(W.M[t.term[e]]), s);
-      out[L.off[m] + part * L.d[m] + (l - m) * L.nb + b] = s;
+      out[L.off[m] + part * L.d[m] + L.pos(m, l, b)] = s;
     }
   }
 

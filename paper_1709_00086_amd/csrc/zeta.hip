@@ -288,7 +288,7 @@ __global__ void k_zeta_accum_mt(const CT* __restrict__ C, int nsub, MDims d, Row
     }
     return d.cw[m] + i * W + j;
   };
-  const int P = (l - m) * nb + b1, Pp = (lp - m) * nb + b2;
+  const int P = L.pos(m, l, b1), Pp = L.pos(m, lp, b2);
   const int dm = L.d[m];
   const int Q = dm + P, Qp = dm + Pp;
   const int iPP = at(P, Pp);
@@ -402,7 +402,7 @@ __global__ void k_zeta_accum(const CT* __restrict__ C, Dims d, RowLayout L,
   const int m = int(t);
   if (l < m || lp < m) return;
   const int W = d.W[m];
-  const int P = (l - m) * nb + b1, Pp = (lp - m) * nb + b2;
+  const int P = L.pos(m, l, b1), Pp = L.pos(m, lp, b2);
   double re = 0.0, im = 0.0;
   for (int s = 0; s < kZetaSplitK; ++s) {
     const CT* c = C + (long long)s * d.csize + d.cw[m];
