@@ -402,19 +402,29 @@ struct PairKernel {
 
   // Candidate of each lane in the window [v0, v0 + 64) of the chunk's runs
   // (lanes past the end repeat the last candidate).  kb is the run holding v0
-  // on entry and the run holding v0 + 63 on return.
+  // on entry and the run holding v0 + 63 on return.  The run starts are read
+  // from a register cache: lane i holds pre[kbase + i] (INT_MAX past the last
+  // run), reloaded only when a window may reach past the cached runs.
   static __device__ __forceinline__ int map_window(const Lds& W, int nrun, int total, int v0,
-                                                   int& kb, Real ref[3]) {
+                                                   int& kb, int& kbase, int& prec, Real ref[3]) {
     const int lane = threadIdx.x % kWave;
     const int vc = min(v0 + lane, total - 1);
-    const int kk = kb + lane;
-    const int prel = kk < nrun ? W.pre[kk] : INT_MAX;
-    // runs kb .. kb + c - 1 overlap the window
-    const int c = __popcll(ballot(prel <= min(v0 + kWave - 1, total - 1)));
+    const int vend = min(v0 + kWave - 1, total - 1);
+    // cached runs that start at or before the window's last candidate (the
+    // starts increase, so these are the lanes below `upto`)
+    int upto = __popcll(ballot(prec <= vend));
+    if (upto == kWave && kbase + kWave < nrun && kb > kbase) {
+      kbase = kb;
+      prec = (kbase + lane < nrun) ? W.pre[kbase + lane] : INT_MAX;
+      upto = __popcll(ballot(prec <= vend));
+    }
+    // runs kb .. kb + c - 1 overlap the window (at most 64 of them)
+    const int r0 = kb - kbase;
+    const int c = upto - r0;
     int koff = 0;
-    int prek = __builtin_amdgcn_readlane(prel, 0);
+    int prek = __builtin_amdgcn_readlane(prec, r0);
     for (int i = 1; i < c; ++i) {
-      const int s = __builtin_amdgcn_readlane(prel, i);
+      const int s = __builtin_amdgcn_readlane(prec, r0 + i);
       const bool ge = vc >= s;
       koff += ge ? 1 : 0;
       prek = ge ? s : prek;
@@ -498,7 +508,8 @@ struct PairKernel {
       int total = 0;
       const int nrun = build_runs(a, cs, P, r0sq, r1sq, c0, nyr, inv_nyr, rb, nrows, W, total);
       if (total == 0) continue;
-      int kb = 0;
+      int kb = 0, kbase = 0;
+      int prec = lane < nrun ? W.pre[lane] : INT_MAX;
       // bin one window and append its accepted pairs to the ring; consume a
       // full wave of pairs when there is one
       auto step = [&](const V& q, const Real* rref, int j, int v0) {
@@ -557,13 +568,13 @@ struct PairKernel {
       // nothing.
       Real refa[3] = {P.pref[0], P.pref[1], P.pref[2]};
       Real refb[3] = {P.pref[0], P.pref[1], P.pref[2]};
-      int ja = map_window(W, nrun, total, 0, kb, refa);
+      int ja = map_window(W, nrun, total, 0, kb, kbase, prec, refa);
       V qa = pos4[ja];
       for (int v0 = 0; v0 < total; v0 += 2 * kWave) {
-        const int jb = map_window(W, nrun, total, v0 + kWave, kb, refb);
+        const int jb = map_window(W, nrun, total, v0 + kWave, kb, kbase, prec, refb);
         const V qb = pos4[jb];
         step(qa, refa, ja, v0);
-        ja = map_window(W, nrun, total, v0 + 2 * kWave, kb, refa);
+        ja = map_window(W, nrun, total, v0 + 2 * kWave, kb, kbase, prec, refa);
         qa = pos4[ja];
         step(qb, refb, jb, v0 + kWave);
       }
