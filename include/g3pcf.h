@@ -61,7 +61,9 @@ typedef enum {
 
 typedef enum {
   G3PCF_PREC_FP64 = 0,    /* plain FP64 throughout                             */
-  G3PCF_PREC_FP32 = 1,    /* pair stage: FP32 accumulation; zeta stage: FP32 MFMA */
+  G3PCF_PREC_FP32 = 1,    /* pair stage: FP32 accumulation (the adjoint also sums
+                             each galaxy's secondary terms in FP32); zeta stage:
+                             FP32 MFMA                                            */
   G3PCF_PREC_BF16X3 = 2   /* zeta stage only: each FP32 operand split into three
                              bfloat16 terms, the six products with i+j <= 2 on
                              BF16 MFMA with FP32 accumulation                   */

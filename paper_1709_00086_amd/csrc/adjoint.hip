@@ -236,12 +236,14 @@ __global__ __launch_bounds__(kFinThreads) void k_adj_finish(AdjArgs a, AdjDims d
   }
 }
 
-__global__ void k_unpermute(const double* __restrict__ gs, const int* __restrict__ perm,
-                            int64_t n, int accumulate, double* __restrict__ grad) {
+__global__ void k_unpermute(const double* __restrict__ gs, const float* __restrict__ gs32,
+                            const int* __restrict__ perm, int64_t n, int accumulate,
+                            double* __restrict__ grad) {
   const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (s >= n) return;
   const int i = perm[s];
-  grad[i] = accumulate ? grad[i] + gs[s] : gs[s];
+  const double g = gs32 ? gs[s] + double(gs32[s]) : gs[s];
+  grad[i] = accumulate ? grad[i] + g : g;
 }
 
 }  // namespace
@@ -269,11 +271,11 @@ hipError_t launch_adj_coef(const AdjArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_unpermute(const double* gs, const int* perm, int64_t n, int accumulate,
-                            double* grad, hipStream_t st) {
+hipError_t launch_unpermute(const double* gs, const float* gs32, const int* perm, int64_t n,
+                            int accumulate, double* grad, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_unpermute, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, gs, perm,
-                     n, accumulate, grad);
+  hipLaunchKernelGGL(k_unpermute, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, gs, gs32,
+                     perm, n, accumulate, grad);
   return hipGetLastError();
 }
 

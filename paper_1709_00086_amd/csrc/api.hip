@@ -62,7 +62,7 @@ size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Ws {
   size_t pos4, tmp4, cid, perm, tmp_perm, wsort, cell_start, cell_count, flags, plist, scan,
-      counters, spill, A, C, ops, gcoef, gsort, mht, hrows;
+      counters, spill, A, C, ops, gcoef, gsort, gsort32, mht, hrows;
   size_t scan_bytes;
   size_t total;
   int64_t PB;   // primaries per pair-block
@@ -113,6 +113,7 @@ Ws plan(const g3pcf_problem& p, int backward) {
     const int T = (p.basis == G3PCF_BASIS_SPIN) ? kTermsSpin : kTermsCart;
     w.gcoef = take(size_t(w.PB) * p.nbins * T * 8);
     w.gsort = take(size_t(n) * 8);
+    w.gsort32 = take(fp64 ? 0 : size_t(n) * 4);  // FP32 secondary terms (FP32 pair path)
     w.mht = take(adj_matrix_doubles(w.lay) * 8);
     w.hrows = take(size_t(w.PB) * w.lay.W * 8);
   }
@@ -416,6 +417,10 @@ int g3pcf_backward(const g3pcf_problem* prob, const double* grad_zeta, double* g
   double* gsort = at<double>(ws, w.gsort);
   if ((e = launch_fill_double(gsort, p.n, 0.0, st)) != hipSuccess)
     return hip_fail(e, "gradient clear");
+  // FP32 pair path: the secondary terms are summed in FP32 on their own array
+  float* gsort32 = (p.pair_prec == G3PCF_PREC_FP64) ? nullptr : at<float>(ws, w.gsort32);
+  if (gsort32 && (e = launch_fill_int(reinterpret_cast<int*>(gsort32), p.n, 0, st)) != hipSuccess)
+    return hip_fail(e, "gradient clear");
   {
     StageScope sc(p.trace, G3PCF_STAGE_ADJ_COEF, st);
     if ((e = launch_adj_matrix(grad_zeta, w.lay, at<double>(ws, w.mht), st)) != hipSuccess)
@@ -428,6 +433,7 @@ int g3pcf_backward(const g3pcf_problem* prob, const double* grad_zeta, double* g
   if ((e = conv_table_device(p.basis, &tab)) != hipSuccess) return hip_fail(e, "table address");
   a.gcoef = at<double>(ws, w.gcoef);
   a.grad_w = gsort;
+  a.grad_w32 = gsort32;
   for (int64_t b0 = 0; b0 < p.n; b0 += w.PB) {
     a.p_begin = b0;
     a.p_count = std::min<int64_t>(w.PB, p.n - b0);
@@ -464,7 +470,8 @@ int g3pcf_backward(const g3pcf_problem* prob, const double* grad_zeta, double* g
         return hip_fail(e, "pair adjoint kernel");
     }
   }
-  if ((e = launch_unpermute(gsort, a.perm, p.n, p.accumulate, grad_w, st)) != hipSuccess)
+  if ((e = launch_unpermute(gsort, gsort32, a.perm, p.n, p.accumulate, grad_w, st)) !=
+      hipSuccess)
     return hip_fail(e, "gradient permute");
   return finish_pairs(p, w, ws, st);
 }

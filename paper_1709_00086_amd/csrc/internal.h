@@ -114,7 +114,8 @@ struct PairArgs {
   // adjoint
   const double* gcoef;       // [p_count][nbins][T] monomial-space adjoint coefficients
   const int* perm;           // [n] slot -> original index
-  double* grad_w;            // [n] original order
+  double* grad_w;            // [n] cell order: FP64 pair path (secondary terms added atomically)
+  float* grad_w32;           // [n] cell order: FP32 pair path (secondary terms added atomically)
   const double* wsort;       // [n] weights in cell order (FP64)
 };
 
@@ -174,8 +175,9 @@ struct AdjArgs {
 size_t adj_matrix_doubles(const RowLayout& L);
 hipError_t launch_adj_matrix(const double* gz, const RowLayout& L, double* MHt, hipStream_t st);
 hipError_t launch_adj_coef(const AdjArgs& a, hipStream_t st);
-hipError_t launch_unpermute(const double* gs, const int* perm, int64_t n, int accumulate,
-                            double* grad, hipStream_t st);
+// grad[perm[s]] (=|+=) gs[s] (+ gs32[s] when gs32 is not null)
+hipError_t launch_unpermute(const double* gs, const float* gs32, const int* perm, int64_t n,
+                            int accumulate, double* grad, hipStream_t st);
 // Device address of the uploaded conversion table of a basis.
 hipError_t conv_table_device(int basis, const ConvTable** out);
 
