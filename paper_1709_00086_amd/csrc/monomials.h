@@ -448,7 +448,11 @@ template <typename Real, int BASIS>
 struct Chunks;
 template <>
 struct Chunks<float, G3PCF_BASIS_CARTESIAN> {
-  using type = ChunkList<CartChunk<float, 0x023u>, CartChunk<float, 0x7DCu>>;
+  // z powers {0, 5, 9, 10}, {1, 4, 7, 8}, {2, 3, 6}: 91, 99 and 96 sums, so
+  // that each chunk fits three waves per SIMD (two chunks at two waves
+  // measured 7% slower)
+  using type = ChunkList<CartChunk<float, 0x621u>, CartChunk<float, 0x192u>,
+                         CartChunk<float, 0x04Cu>>;
 };
 template <>
 struct Chunks<double, G3PCF_BASIS_CARTESIAN> {

@@ -237,7 +237,7 @@ struct Bin64 {
 template <typename Real, int BASIS, bool ADJOINT>
 struct Occ {
   static constexpr int value =
-      ADJOINT ? 4 : ((std::is_same<Real, float>::value && BASIS == G3PCF_BASIS_SPIN) ? 3 : 2);
+      ADJOINT ? 4 : (std::is_same<Real, float>::value ? 3 : 2);
 };
 
 template <class... C>
