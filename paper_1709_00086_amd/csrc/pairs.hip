@@ -15,8 +15,9 @@
 //      periodic box).  All cell-start lookups of the 64 rows are in flight at
 //      once, and the runs go into a table in LDS with their prefix sums;
 //   2. streams the runs' galaxies with one candidate per lane (a lane finds
-//      its run from the prefix sums; the next window's loads are in flight
-//      while one is binned), bins each candidate, and appends the accepted
+//      its run among the run starts, which the wave keeps in a register; the
+//      next window's loads are in flight while one is binned), bins each
+//      candidate with the shell's squared edges, and appends the accepted
 //      separations to a ring of pairs in LDS -- the GPU form of the paper's
 //      per-bin pair buckets;
 //   3. whenever the ring holds a full wave of pairs, normalises and rotates
@@ -31,7 +32,8 @@
 // which the later chunks replay (a repeated search if the list overflowed).
 //
 // The adjoint kernel runs the same search and, per accepted pair, evaluates
-// the shell's adjoint polynomial and adds it to the secondary's gradient.
+// the shell's adjoint polynomial in FP64 and adds it to the secondary's
+// gradient with one atomic (FP32 on the FP32 path, FP64 on the FP64 path).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
