@@ -47,7 +47,7 @@ def _load():
         lib.oracle_ylm.restype = None
         common = [i64, vp, vp, vp, vp, ctypes.c_int, vp, d, ctypes.c_int, ctypes.c_int,
                   ctypes.c_int, vp]
-        lib.oracle_zeta.argtypes = common + [vp, vp, ctypes.c_int]
+        lib.oracle_zeta.argtypes = common + [vp, vp, ctypes.c_int, ctypes.c_int]
         lib.oracle_zeta.restype = ctypes.c_int
         lib.oracle_grad.argtypes = common + [vp, vp, ctypes.c_int]
         lib.oracle_grad.restype = ctypes.c_int
@@ -92,14 +92,19 @@ def _args(cat, primary_mask):
                   _p(obs), float(cat.rmax), int(cat.nbins), int(cat.lmax), los, _p(mask)]
 
 
-def zeta(cat, primary_mask=None, nthreads: int | None = None, return_pairs: bool = False):
-    """zeta^m_{l l'}(b1, b2) as float64 [m][l][l'][b1][b2][re, im]."""
+def zeta(cat, primary_mask=None, nthreads: int | None = None, return_pairs: bool = False,
+         distinct: bool = False):
+    """zeta^m_{l l'}(b1, b2) as float64 [m][l][l'][b1][b2][re, im].
+
+    ``distinct`` leaves out the degenerate triangles j = k (the same secondary
+    on both sides), which the product of the a_lm (Sec. 3.1) contains."""
     lib = _load()
     keep, args = _args(cat, primary_mask)
     shape = (cat.lmax + 1, cat.lmax + 1, cat.lmax + 1, cat.nbins, cat.nbins, 2)
     out = np.zeros(shape, dtype=np.float64)
     pairs = np.zeros(1, dtype=np.int64)
-    rc = lib.oracle_zeta(*args, _p(out), _p(pairs), int(nthreads or default_threads()))
+    rc = lib.oracle_zeta(*args, _p(out), _p(pairs), int(nthreads or default_threads()),
+                         int(bool(distinct)))
     del keep
     if rc != 0:
         raise ValueError(f"oracle_zeta failed with code {rc}")
@@ -116,4 +121,22 @@ def grad(cat, c, primary_mask=None, nthreads: int | None = None) -> np.ndarray:
     del keep
     if rc != 0:
         raise ValueError(f"oracle_grad failed with code {rc}")
+    return out
+
+
+def isotropic(z) -> np.ndarray:
+    """Isotropic multipoles zeta_l(b1, b2) = sum_i w_i sum_{j in b1, k in b2}
+    w_j w_k P_l(u_ij . u_ik), shape [l][b1][b2], from the anisotropic ones by the
+    addition theorem (Sec. 2: the Legendre polynomial of the opening angle is
+    4 pi / (2l + 1) times the sum over m of Y_lm Y*_lm):
+    zeta_l = 4 pi / (2l + 1) [zeta^0_ll + 2 sum_{m >= 1} Re zeta^m_ll]
+    (zeta^{-m} is the conjugate of zeta^m for real weights)."""
+    z = np.asarray(z, dtype=np.float64)
+    lmax, nb = z.shape[0] - 1, z.shape[3]
+    out = np.zeros((lmax + 1, nb, nb))
+    for l in range(lmax + 1):
+        s = z[0, l, l, :, :, 0].copy()
+        for m in range(1, l + 1):
+            s = s + 2.0 * z[m, l, l, :, :, 0]
+        out[l] = 4.0 * np.pi / (2 * l + 1) * s
     return out

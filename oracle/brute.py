@@ -85,9 +85,9 @@ def ylm_matrix(u, lmax):
     return Y
 
 
-def zeta_triplets(cat, primary_mask=None, azimuth_seed=None):
+def zeta_triplets(cat, primary_mask=None, azimuth_seed=None, distinct=False):
     """zeta from an explicit sum over ordered triplets (i, j, k), j, k != i,
-    j = k included, with no factorisation through a_lm:
+    j = k included (left out with ``distinct``), with no factorisation through a_lm:
       zeta^m_{ll'}(b_ij, b_ik) += w_i w_j w_k conj(Y_lm(u_ij)) Y_l'm(u_ik)."""
     lmax, nb = cat.lmax, cat.nbins
     z = np.zeros((lmax + 1, lmax + 1, lmax + 1, nb, nb), dtype=np.complex128)
@@ -103,6 +103,8 @@ def zeta_triplets(cat, primary_mask=None, azimuth_seed=None):
         # every ordered triplet (i, j, k): T[j, k, m, l, l'] = conj(Y_lm(u_ij)) Y_l'm(u_ik)
         T = np.einsum("jam,kbm->jkmab", np.conj(Y), Y)
         f = w[i] * np.outer(wj, wj)
+        if distinct:
+            np.fill_diagonal(f, 0.0)
         T = T * f[:, :, None, None, None]
         bj = np.repeat(b, j.size)
         bk = np.tile(b, j.size)
@@ -116,8 +118,9 @@ def zeta_triplets(cat, primary_mask=None, azimuth_seed=None):
     return out
 
 
-def isotropic_triplets(cat, primary_mask=None):
-    """sum_i w_i sum_{j in b1, k in b2} w_j w_k P_l(u_ij . u_ik), shape [l][b1][b2]."""
+def isotropic_triplets(cat, primary_mask=None, distinct=False):
+    """sum_i w_i sum_{j in b1, k in b2} w_j w_k P_l(u_ij . u_ik), shape [l][b1][b2]
+    (j = k left out with ``distinct``)."""
     lmax, nb = cat.lmax, cat.nbins
     out = np.zeros((lmax + 1, nb, nb))
     w = np.asarray(cat.w, dtype=np.float64)
@@ -128,6 +131,8 @@ def isotropic_triplets(cat, primary_mask=None):
             continue
         mu = np.clip(u @ u.T, -1.0, 1.0)
         ww = w[i] * np.outer(w[j], w[j])
+        if distinct:
+            np.fill_diagonal(ww, 0.0)
         for l in range(lmax + 1):
             P = eval_legendre(l, mu) * ww
             np.add.at(out[l], (b[:, None].repeat(j.size, 1), b[None, :].repeat(j.size, 0)), P)

@@ -226,11 +226,15 @@ void oracle_ylm(double ux, double uy, double uz, int lmax, double* out) {
 }
 
 // zeta: dense [m][l][l'][b1][b2][re,im], zero where l < m or l' < m.
+// distinct = 1 leaves out the degenerate triangles j = k (the same secondary on
+// both sides, so b1 = b2): their terms w_i w_j^2 conj(Y_lm(u_ij)) Y_l'm(u_ij)
+// are subtracted from the product of the a_lm (Sec. 3.1 writes zeta as that
+// product, which contains them).
 // Returns 0, or -1 on invalid arguments, -2 if a primary sits on the observer.
 int oracle_zeta(int64_t n, const double* pos, const double* w, const double* L,
                 const double* lo, int periodic, const double* obs, double rmax, int nbins,
                 int lmax, int los, const uint8_t* mask, double* zeta, int64_t* pairs_out,
-                int nthreads) {
+                int nthreads, int distinct) {
   Problem p{n, pos, w, {L[0], L[1], L[2]}, {lo[0], lo[1], lo[2]}, periodic,
             {obs[0], obs[1], obs[2]}, rmax, nbins, lmax, los, mask};
   if (check(p)) return -1;
@@ -269,6 +273,21 @@ int oracle_zeta(int64_t n, const double* pos, const double* w, const double* L,
                 o[0] += v.real();
                 o[1] += v.imag();
               }
+      if (distinct) {
+        // the j = k terms, one secondary at a time
+        ctx.neighbours(i, R, [&](int64_t j, int b, const double* u) {
+          ylm(u[0], u[1], u[2], lmax, y.data());
+          const double f = wi * w[j] * w[j];
+          for (int m = 0; m <= lmax; ++m)
+            for (int l = m; l <= lmax; ++l)
+              for (int lp = m; lp <= lmax; ++lp) {
+                const cd v = f * std::conj(y[lm_index(l, m)]) * y[lm_index(lp, m)];
+                double* o = z + zidx(lmax, nbins, m, l, lp, b, b);
+                o[0] -= v.real();
+                o[1] -= v.imag();
+              }
+        });
+      }
     }
   }
   if (err) return err;
