@@ -78,6 +78,9 @@ def main():
     ap.add_argument("--basis", default="spin", choices=["cartesian", "spin"])
     ap.add_argument("--forward-only", action="store_true",
                     help="time the forward pass only (not the contract's step)")
+    ap.add_argument("--distinct", action="store_true",
+                    help="leave out the degenerate j = k triangles (forward only, so it "
+                         "implies --forward-only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--sample", type=int, default=8192,
@@ -86,6 +89,8 @@ def main():
                     help="first run one plain device copy of MIB MiB (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
+    if args.distinct:
+        args.forward_only = True
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus > 1 or world > 1:
@@ -113,7 +118,7 @@ def main():
     w = torch.from_numpy(cat.w).to(dev)
     cfg = api.Config(box=cat.box, rmax=cat.rmax, nbins=cat.nbins, lmax=cat.lmax, los=cat.los,
                      observer=cat.observer, periodic=cat.periodic, box_lo=cat.box_lo,
-                     precision=args.precision, basis=args.basis)
+                     precision=args.precision, basis=args.basis, distinct=args.distinct)
     c = torch.from_numpy(C.loss_weights(cat.lmax, cat.nbins, seed=55)).to(dev)
     ws = api.Workspace()
     zeta_out = torch.empty(api.zeta_shape(cat.lmax, cat.nbins), dtype=torch.float64, device=dev)
@@ -186,6 +191,7 @@ def main():
             "precision": args.precision,
             "basis": args.basis,
             "step": "forward" if args.forward_only else "forward+backward",
+            "distinct": bool(args.distinct),
             "accepted_pairs": pairs,
         },
         "stage_ms_per_step": stage_ms,
@@ -221,7 +227,7 @@ def main():
         threads = oracle.default_threads()
         t = time.perf_counter()
         ref, ref_pairs = oracle.zeta(cat, primary_mask=mask_np, nthreads=threads,
-                                     return_pairs=True)
+                                     return_pairs=True, distinct=args.distinct)
         dt = time.perf_counter() - t
         out["cpu_baseline"] = {
             "value": ref_pairs / dt,
@@ -239,7 +245,8 @@ def main():
     if not args.no_fp64_compare and args.precision != "fp64":
         cfg64 = api.Config(box=cat.box, rmax=cat.rmax, nbins=cat.nbins, lmax=cat.lmax,
                            los=cat.los, observer=cat.observer, periodic=cat.periodic,
-                           box_lo=cat.box_lo, precision="fp64", basis=args.basis)
+                           box_lo=cat.box_lo, precision="fp64", basis=args.basis,
+                           distinct=args.distinct)
         api.zeta(pos, w, cfg64, out=zeta_out, workspace=ws)
         torch.cuda.synchronize()
         t = time.perf_counter()

@@ -84,7 +84,8 @@ typedef enum {
   G3PCF_STAGE_PAIRS = 1,        /* pair kernel: search, rotate, bin, accumulate, convert */
   G3PCF_STAGE_ZETA = 2,         /* Gram products on MFMA + FP64 accumulation       */
   G3PCF_STAGE_ADJ_COEF = 3,     /* adjoint: U, V, H and monomial coefficients      */
-  G3PCF_STAGE_PAIR_ADJOINT = 4  /* adjoint pair kernel: polynomial + scatter        */
+  G3PCF_STAGE_PAIR_ADJOINT = 4, /* adjoint pair kernel: polynomial + scatter        */
+  G3PCF_STAGE_DISTINCT = 5      /* degenerate-triangle pass, sums and correction   */
 } g3pcf_stage;
 
 /* Opaque record of per-stage GPU time.  Created on the current device. */
@@ -119,6 +120,13 @@ typedef struct {
   g3pcf_trace* trace;      /* HOST handle or NULL.  If set, a pair of HIP events is
                               recorded on `stream` around every stage launch
                               (no synchronisation); read with g3pcf_trace_read */
+  int distinct;            /* 0: zeta as the product of the a_lm (Sec. 3.1), which
+                              contains the degenerate triangles j = k (the same
+                              secondary on both sides, b1 = b2).  1: leave them
+                              out, i.e. subtract sum_i w_i sum_j w_j^2
+                              conj(Y_lm(u_ij)) Y_l'm(u_ij) at b1 = b2 = b_ij
+                              (a second pass over the pairs; forward only:
+                              g3pcf_backward returns G3PCF_EUNSUPPORTED)     */
 } g3pcf_problem;
 
 /* Trace with room for `capacity` stage records (2 * capacity HIP events on the
@@ -182,6 +190,24 @@ int g3pcf_forward(const g3pcf_problem* prob, double* zeta, void* ws, size_t ws_b
  * g3pcf_workspace_bytes(prob, 1) bytes.  Same errors as g3pcf_forward. */
 int g3pcf_backward(const g3pcf_problem* prob, const double* grad_zeta, double* grad_w,
                    void* ws, size_t ws_bytes, void* stream);
+
+/* Isotropic multipoles from zeta by the addition theorem (the Legendre
+ * polynomial of the angle between two directions is 4 pi / (2l + 1) times the
+ * sum over m of Y_lm Y*_lm, Sec. 2):
+ *   iso[l][b1][b2] = 4 pi / (2l + 1) (zeta^0_ll + 2 sum_{m >= 1} Re zeta^m_ll)(b1, b2)
+ *                  = sum_i w_i sum_{j in b1, k in b2} w_j w_k P_l(u_ij . u_ik).
+ * zeta: device, laid out as g3pcf_forward writes it for (lmax, nbins);
+ * iso: device, [lmax+1][nbins][nbins] doubles, overwritten.  Asynchronous on
+ * `stream`.  Returns G3PCF_OK, G3PCF_EINVAL (lmax outside 0..10, nbins outside
+ * 1..32, NULL pointers) or G3PCF_EHIP. */
+int g3pcf_isotropic(int lmax, int nbins, const double* zeta, double* iso, void* stream);
+
+/* Diagnostic, host only, no device use: the degenerate-triangle term
+ * conj(Y_lm(u)) Y_l'm(u) (real; it depends on u_z alone) as the library's
+ * distinct = 1 correction represents it, a Legendre series in u_z.
+ * out: HOST array [lmax+1][lmax+1][lmax+1] as [m][l][l'], zero where l < m or
+ * l' < m.  Returns G3PCF_OK or G3PCF_EINVAL (lmax outside 0..10, NULL). */
+int g3pcf_degenerate_term(int lmax, double uz, double* out);
 
 /* Message for the last non-OK return on this thread ("" if none). */
 const char* g3pcf_last_error(void);

@@ -20,8 +20,8 @@ BASIS_CARTESIAN, BASIS_SPIN = 0, 1
 EXPORTED = ["g3pcf_zeta_len", "g3pcf_num_terms", "g3pcf_workspace_bytes", "g3pcf_forward",
             "g3pcf_backward", "g3pcf_last_error", "g3pcf_conj_ylm_via_monomials",
             "g3pcf_trace_create", "g3pcf_trace_reset", "g3pcf_trace_read",
-            "g3pcf_trace_destroy"]
-STAGES = {0: "cells", 1: "pairs", 2: "zeta", 3: "adj_coef", 4: "pair_adjoint"}
+            "g3pcf_trace_destroy", "g3pcf_isotropic", "g3pcf_degenerate_term"]
+STAGES = {0: "cells", 1: "pairs", 2: "zeta", 3: "adj_coef", 4: "pair_adjoint", 5: "distinct"}
 
 
 class Problem(ctypes.Structure):
@@ -45,6 +45,7 @@ class Problem(ctypes.Structure):
         ("accumulate", ctypes.c_int),
         ("pairs_out", ctypes.POINTER(ctypes.c_int64)),
         ("trace", ctypes.c_void_p),
+        ("distinct", ctypes.c_int),
     ]
 
 
@@ -96,6 +97,12 @@ def load():
     lib.g3pcf_trace_read.restype = ctypes.c_int
     lib.g3pcf_trace_destroy.argtypes = [ctypes.c_void_p]
     lib.g3pcf_trace_destroy.restype = None
+    lib.g3pcf_isotropic.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_void_p]
+    lib.g3pcf_isotropic.restype = ctypes.c_int
+    lib.g3pcf_degenerate_term.argtypes = [ctypes.c_int, ctypes.c_double,
+                                          ctypes.POINTER(ctypes.c_double)]
+    lib.g3pcf_degenerate_term.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -138,6 +145,15 @@ def conj_ylm_via_monomials(basis: int, lmax: int, u) -> list:
     check(load().g3pcf_conj_ylm_via_monomials(int(basis), int(lmax), float(u[0]), float(u[1]),
                                               float(u[2]), out))
     return [complex(out[2 * k], out[2 * k + 1]) for k in range(n // 2)]
+
+
+def degenerate_term(lmax: int, uz: float) -> list:
+    """conj(Y_lm(u)) Y_l'm(u) as [m][l][l'] nested lists (host diagnostic)."""
+    L1 = lmax + 1
+    out = (ctypes.c_double * (L1 * L1 * L1))()
+    check(load().g3pcf_degenerate_term(int(lmax), float(uz), out))
+    return [[[out[(m * L1 + l) * L1 + lp] for lp in range(L1)] for l in range(L1)]
+            for m in range(L1)]
 
 
 class Trace:

@@ -35,6 +35,7 @@ class Config:
     precision: str = "fp32"            # "fp64", "fp32" or "bf16x3"
     zeta_precision: Optional[str] = None  # override the zeta-stage precision
     basis: str = "cartesian"           # "cartesian" (eq. 1 monomials) or "spin"
+    distinct: bool = False             # leave out the degenerate triangles j = k (forward only)
 
     def pair_prec(self) -> int:
         return _PREC[self.precision][0]
@@ -94,6 +95,7 @@ def make_problem(pos: torch.Tensor, w: torch.Tensor, cfg: Config,
     p.accumulate = 1 if accumulate else 0
     p.pairs_out = pairs_out
     p.trace = trace.handle if trace is not None else None
+    p.distinct = 1 if cfg.distinct else 0
     return p
 
 
@@ -150,6 +152,24 @@ def zeta_backward(pos: torch.Tensor, w: torch.Tensor, cfg: Config, grad_zeta: to
     stream = torch.cuda.current_stream(pos.device).cuda_stream
     _lib.backward(p, gz.data_ptr(), gw.data_ptr(), ws.data_ptr(), ws.numel(), stream)
     return gw
+
+
+def isotropic(zeta_t: torch.Tensor, lmax: int, nbins: int) -> torch.Tensor:
+    """Isotropic multipoles [l][b1][b2] from zeta by the addition theorem, on the
+    library's kernel: 4 pi / (2l + 1) (zeta^0_ll + 2 sum_{m >= 1} Re zeta^m_ll)."""
+    import ctypes
+    _require_cuda(zeta_t, "zeta")
+    if (zeta_t.shape != zeta_shape(lmax, nbins) or zeta_t.dtype != torch.float64
+            or not zeta_t.is_contiguous()):
+        raise ValueError("zeta must be a contiguous float64 tensor of shape "
+                         + str(zeta_shape(lmax, nbins)))
+    out = torch.empty((lmax + 1, nbins, nbins), dtype=torch.float64, device=zeta_t.device)
+    stream = torch.cuda.current_stream(zeta_t.device).cuda_stream
+    _lib.check(_lib.load().g3pcf_isotropic(int(lmax), int(nbins),
+                                           ctypes.c_void_p(zeta_t.data_ptr()),
+                                           ctypes.c_void_p(out.data_ptr()),
+                                           ctypes.c_void_p(stream)))
+    return out
 
 
 class G3PCF(torch.autograd.Function):

@@ -62,7 +62,7 @@ size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Ws {
   size_t pos4, tmp4, cid, perm, tmp_perm, wsort, cell_start, cell_count, flags, plist, scan,
-      counters, spill, A, C, ops, gcoef, gsort, gsort32, mht, hrows;
+      counters, spill, A, C, ops, gcoef, gsort, gsort32, mht, hrows, degD, degP;
   size_t scan_bytes;
   size_t total;
   int64_t PB;   // primaries per pair-block
@@ -109,6 +109,10 @@ Ws plan(const g3pcf_problem& p, int backward) {
   w.C = take(zeta_partial_doubles(w.lay) * 8);
   w.ops = (!backward && p.zeta_prec == G3PCF_PREC_BF16X3) ? take(size_t(6) * w.lay.W * w.Kp * 2)
                                                            : take(0);
+  // degenerate triangles: per-shell Legendre sums and their per-workgroup partials
+  const bool deg = !backward && p.distinct;
+  w.degD = take(deg ? size_t(p.nbins) * (2 * p.lmax + 1) * 8 : 0);
+  w.degP = take(deg ? deg_partial_doubles(w.PB, p.nbins, p.lmax) * 8 : 0);
   if (backward) {
     const int T = (p.basis == G3PCF_BASIS_SPIN) ? kTermsSpin : kTermsCart;
     w.gcoef = take(size_t(w.PB) * p.nbins * T * 8);
@@ -154,6 +158,8 @@ int validate(const g3pcf_problem* p) {
     return fail(G3PCF_EINVAL, "zeta_prec must be FP64, FP32 or BF16X3");
   if (p->basis != G3PCF_BASIS_CARTESIAN && p->basis != G3PCF_BASIS_SPIN)
     return fail(G3PCF_EINVAL, "basis must be G3PCF_BASIS_CARTESIAN or G3PCF_BASIS_SPIN");
+  if (p->distinct != 0 && p->distinct != 1)
+    return fail(G3PCF_EINVAL, "distinct must be 0 or 1");
   if (p->accumulate != 0 && p->accumulate != 1)
     return fail(G3PCF_EINVAL, "accumulate must be 0 or 1");
   return G3PCF_OK;
@@ -168,8 +174,8 @@ int ensure_tables(int basis) {
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   std::lock_guard<std::mutex> lk(g_tab_mu);
   if (g_tab_done.count({dev, basis})) return G3PCF_OK;
-  e = upload_tables(basis);
-  if (e != hipSuccess) return hip_fail(e, "conversion table upload");
+  e = (basis == kBasisDeg) ? upload_deg_table() : upload_tables(basis);
+  if (e != hipSuccess) return hip_fail(e, "table upload");
   g_tab_done.insert({dev, basis});
   return G3PCF_OK;
 }
@@ -183,7 +189,8 @@ struct Counters {
   long long nprim;
   unsigned long long pairs;
   unsigned long long pairs_adj;
-  int pad[10];
+  unsigned long long pairs_deg;  // counted again by the degenerate-triangle pass
+  int pad[8];
   int queue[kQueues * kQueueStride];  // one primary counter per XCD, 64 B apart
 };
 static_assert(sizeof(Counters) <= kCountersBytes, "counters block");
@@ -348,6 +355,7 @@ int g3pcf_forward(const g3pcf_problem* prob, double* zeta, void* ws, size_t ws_b
     return fail(G3PCF_EWORKSPACE, "workspace must be 256-byte aligned");
   hipStream_t st = static_cast<hipStream_t>(stream);
   if ((rc = ensure_tables(p.basis))) return rc;
+  if (p.distinct && (rc = ensure_tables(kBasisDeg))) return rc;
   const size_t zlen = g3pcf_zeta_len(p.lmax, p.nbins);
   hipError_t e;
   if (!p.accumulate && (e = launch_fill_double(zeta, int64_t(zlen), 0.0, st)) != hipSuccess)
@@ -363,30 +371,53 @@ int g3pcf_forward(const g3pcf_problem* prob, double* zeta, void* ws, size_t ws_b
   PairArgs a = pair_args(p, w, ws);
   const int fp64 = (p.pair_prec == G3PCF_PREC_FP64);
   Counters* c = at<Counters>(ws, w.counters);
+  double* degD = at<double>(ws, w.degD);
+  if (p.distinct &&
+      (e = launch_fill_double(degD, int64_t(p.nbins) * (2 * p.lmax + 1), 0.0, st)) != hipSuccess)
+    return hip_fail(e, "degenerate sums clear");
   for (int64_t b0 = 0; b0 < p.n; b0 += w.PB) {
     a.p_begin = b0;
     a.p_count = std::min<int64_t>(w.PB, p.n - b0);
+    a.pairs = &c->pairs;
     {
       StageScope sc(p.trace, G3PCF_STAGE_PAIRS, st);
       if ((e = launch_pair_forward(a, fp64, p.basis, st)) != hipSuccess)
         return hip_fail(e, "pair kernel");
     }
-    StageScope scz(p.trace, G3PCF_STAGE_ZETA, st);
-    ZetaArgs z{};
-    z.A = a.A;
-    z.wsort = a.wsort;
-    z.plist = a.plist;
-    z.nprim = &c->nprim;
-    z.row_begin = b0;
-    z.sub_begin = 0;
-    z.K = a.p_count;
-    z.lay = w.lay;
-    z.ops = at<void>(ws, w.ops);
-    z.C32 = at<float>(ws, w.C);
-    z.C64 = at<double>(ws, w.C);
-    z.zeta = zeta;
-    z.prec = p.zeta_prec;
-    if ((e = launch_zeta_pairblock(z, st)) != hipSuccess) return hip_fail(e, "zeta");
+    {
+      StageScope scz(p.trace, G3PCF_STAGE_ZETA, st);
+      ZetaArgs z{};
+      z.A = a.A;
+      z.wsort = a.wsort;
+      z.plist = a.plist;
+      z.nprim = &c->nprim;
+      z.row_begin = b0;
+      z.sub_begin = 0;
+      z.K = a.p_count;
+      z.lay = w.lay;
+      z.ops = at<void>(ws, w.ops);
+      z.C32 = at<float>(ws, w.C);
+      z.C64 = at<double>(ws, w.C);
+      z.zeta = zeta;
+      z.prec = p.zeta_prec;
+      if ((e = launch_zeta_pairblock(z, st)) != hipSuccess) return hip_fail(e, "zeta");
+    }
+    if (p.distinct) {
+      // the same pairs again for their sums w_j^2 P_n(u_z), written over the
+      // pair-block's A rows (already reduced into zeta), then summed with w_i
+      StageScope scd(p.trace, G3PCF_STAGE_DISTINCT, st);
+      a.pairs = &c->pairs_deg;
+      if ((e = launch_pair_distinct(a, fp64, st)) != hipSuccess)
+        return hip_fail(e, "degenerate-triangle pass");
+      if ((e = launch_deg_reduce(a.A, w.lay.W, p.nbins, p.lmax, a.wsort, a.plist, &c->nprim, b0,
+                                 a.p_count, at<double>(ws, w.degP), degD, st)) != hipSuccess)
+        return hip_fail(e, "degenerate-triangle sums");
+    }
+  }
+  if (p.distinct) {
+    StageScope scd(p.trace, G3PCF_STAGE_DISTINCT, st);
+    if ((e = launch_deg_apply(degD, p.lmax, p.nbins, zeta, st)) != hipSuccess)
+      return hip_fail(e, "degenerate-triangle correction");
   }
   return finish_pairs(p, w, ws, st);
 }
@@ -397,6 +428,8 @@ int g3pcf_backward(const g3pcf_problem* prob, const double* grad_zeta, double* g
   if (rc) return rc;
   if (!grad_zeta || (!grad_w && prob->n > 0))
     return fail(G3PCF_EINVAL, "grad_zeta and grad_w must be non-NULL");
+  if (prob->distinct)
+    return fail(G3PCF_EUNSUPPORTED, "the adjoint does not cover distinct = 1");
   const g3pcf_problem& p = *prob;
   const Ws w = plan(p, 1);
   if (!ws || ws_bytes < w.total)
@@ -474,6 +507,42 @@ int g3pcf_backward(const g3pcf_problem* prob, const double* grad_zeta, double* g
       hipSuccess)
     return hip_fail(e, "gradient permute");
   return finish_pairs(p, w, ws, st);
+}
+
+int g3pcf_isotropic(int lmax, int nbins, const double* zeta, double* iso, void* stream) {
+  if (lmax < 0 || lmax > kDeg) return fail(G3PCF_EINVAL, "lmax must be 0..10");
+  if (nbins < 1 || nbins > kMaxBins) return fail(G3PCF_EINVAL, "nbins must be 1..32");
+  if (!zeta || !iso) return fail(G3PCF_EINVAL, "zeta and iso must be non-NULL");
+  const hipError_t e = launch_isotropic(zeta, lmax, nbins, iso, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? G3PCF_OK : hip_fail(e, "isotropic");
+}
+
+int g3pcf_degenerate_term(int lmax, double uz, double* out) {
+  if (lmax < 0 || lmax > kDeg || !out) return fail(G3PCF_EINVAL, "lmax 0..10 and out required");
+  static std::vector<double> G;
+  static std::mutex mu;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    if (G.empty()) {
+      G.resize(kDegTable);
+      build_deg_table(G.data());
+    }
+  }
+  double pn[kTermsDeg];
+  pn[0] = 1.0;
+  pn[1] = uz;
+  for (int n = 1; n + 1 < kTermsDeg; ++n)
+    pn[n + 1] = ((2.0 * n + 1.0) * uz * pn[n] - n * pn[n - 1]) / (n + 1.0);
+  const int L1 = lmax + 1;
+  for (int m = 0; m <= lmax; ++m)
+    for (int l = 0; l <= lmax; ++l)
+      for (int lp = 0; lp <= lmax; ++lp) {
+        double s = 0.0;
+        if (l >= m && lp >= m)
+          for (int n = 0; n <= l + lp; ++n) s += G[deg_index(m, l, lp, n)] * pn[n];
+        out[(m * L1 + l) * L1 + lp] = s;
+      }
+  return G3PCF_OK;
 }
 
 }  // extern "C"

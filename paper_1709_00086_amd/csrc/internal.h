@@ -16,6 +16,10 @@ namespace g3 {
 constexpr int kDeg = 10;
 constexpr int kTermsCart = (kDeg + 1) * (kDeg + 2) * (kDeg + 3) / 6;  // 286
 constexpr int kTermsSpin = (kDeg + 1) * (kDeg + 1);                   // 121 real sums
+// Internal "basis" of the pass that collects the degenerate (j = k) triangles:
+// per shell the sums w_j^2 P_n(u_z) of Legendre polynomials, n <= 2 kDeg.
+constexpr int kBasisDeg = 2;
+constexpr int kTermsDeg = 2 * kDeg + 1;                               // 21
 constexpr int kMaxBins = 32;
 constexpr int kWave = 64;
 constexpr int kOutPerBin = (kDeg + 1) * (kDeg + 1);  // real a_lm outputs per shell (121)
@@ -53,6 +57,13 @@ struct ConvTable {
 
 // Host: build the conversion table for a basis (0 cartesian, 1 spin).
 void build_conv_table(int basis, ConvTable* t);
+
+// Degenerate-triangle table G[m][l][l'][n]: Pbar_lm Pbar_l'm = sum_n G P_n.
+constexpr int kDegTable = (kDeg + 1) * (kDeg + 1) * (kDeg + 1) * kTermsDeg;
+__host__ __device__ inline int deg_index(int m, int l, int lp, int n) {
+  return ((m * (kDeg + 1) + l) * (kDeg + 1) + lp) * kTermsDeg + n;
+}
+void build_deg_table(double* G);  // host
 
 // Cell grid of the sorted catalogue.
 struct Grid {
@@ -131,6 +142,9 @@ hipError_t launch_fill_int(int* p, int64_t count, int value, hipStream_t st);
 hipError_t launch_fill_double(double* p, int64_t count, double value, hipStream_t st);
 hipError_t launch_pair_forward(const PairArgs& a, int fp64, int basis, hipStream_t st);
 hipError_t launch_pair_adjoint(const PairArgs& a, int fp64, int basis, hipStream_t st);
+// Degenerate-triangle pass: per primary and shell the sums w_j^2 P_n(u_z),
+// n <= 2 lmax, into A[row][shell * (2 lmax + 1) + n] (FP64).
+hipError_t launch_pair_distinct(const PairArgs& a, int fp64, hipStream_t st);
 hipError_t upload_tables(int basis);
 
 struct ZetaArgs {
@@ -186,5 +200,17 @@ hipError_t launch_scan(const int* in, int* out, int64_t count, void* tmp, size_t
                        hipStream_t st);
 
 int sum_wm2(const RowLayout& lay);
+
+// Degenerate triangles (distinct secondaries): table upload, the weighted sum
+// over a pair-block's rows X[r][b (2 lmax + 1) + n] into D (FP64, in order),
+// and the correction of zeta^m_{ll'}(b, b).
+hipError_t upload_deg_table();
+size_t deg_partial_doubles(long long PB, int nb, int lmax);
+hipError_t launch_deg_reduce(const double* X, int rowW, int nb, int lmax, const double* wsort,
+                             const int* plist, const long long* nprim, long long p_begin,
+                             long long p_count, double* partial, double* D, hipStream_t st);
+hipError_t launch_deg_apply(const double* D, int lmax, int nb, double* zeta, hipStream_t st);
+// Isotropic multipoles from zeta (addition theorem).
+hipError_t launch_isotropic(const double* zeta, int lmax, int nb, double* iso, hipStream_t st);
 
 }  // namespace g3

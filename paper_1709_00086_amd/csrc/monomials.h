@@ -468,6 +468,41 @@ struct Chunks<double, G3PCF_BASIS_SPIN> {
   using type = ChunkList<SpinChunk<double, 0, 3>, SpinChunk<double, 4, kDeg>>;
 };
 
+// Degenerate-triangle sums: D_n = sum w^2 P_n(z), n <= 2 kDeg, with the
+// Legendre polynomials from their three-term recurrence (bounded by 1 on
+// [-1, 1], so FP32 is accurate).  conj(Y_lm) Y_l'm depends on z alone and is
+// a polynomial of degree l + l', i.e. a combination of these P_n.
+template <typename Real>
+struct DegChunk {
+  static constexpr int NT = kTermsDeg;
+  Real acc[NT];
+  static __host__ __device__ constexpr int term_of(int i) { return i; }
+
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int i = 0; i < NT; ++i) acc[i] = Real(0);
+  }
+
+  __device__ __forceinline__ void add(Real, Real, Real z, Real w) {
+    const Real w2 = w * w;
+    Real p0 = Real(1), p1 = z;
+    acc[0] += w2;
+    acc[1] = fma_r(w2, p1, acc[1]);
+    static_for<NT - 2>([&](auto nc) {
+      constexpr int n = decltype(nc)::value + 1;  // P_{n+1} from P_n and P_{n-1}
+      constexpr Real a = Real(2 * n + 1) / Real(n + 1), c = Real(n) / Real(n + 1);
+      const Real p2 = fma_r(a * z, p1, -(c * p0));
+      acc[n + 1] = fma_r(w2, p2, acc[n + 1]);
+      p0 = p1;
+      p1 = p2;
+    });
+  }
+};
+template <typename Real>
+struct Chunks<Real, kBasisDeg> {
+  using type = ChunkList<DegChunk<Real>>;
+};
+
 template <class... C, typename F>
 __device__ __forceinline__ void for_each_chunk(ChunkList<C...>, F&& f) {
   (f(static_cast<C*>(nullptr)), ...);

@@ -239,7 +239,7 @@ struct Bin64 {
 template <typename Real, int BASIS, bool ADJOINT>
 struct Occ {
   static constexpr int value =
-      ADJOINT ? 4 : (std::is_same<Real, float>::value ? 3 : 2);
+      (ADJOINT || BASIS == kBasisDeg) ? 4 : (std::is_same<Real, float>::value ? 3 : 2);
 };
 
 template <class... C>
@@ -253,7 +253,9 @@ struct PairKernel {
   using V = typename V4<Real>::T;
   using Lds = WaveLds<Real, ADJOINT>;
   static constexpr bool kF32 = std::is_same<Real, float>::value;
-  static constexpr int kTerms = (BASIS == G3PCF_BASIS_SPIN) ? kTermsSpin : kTermsCart;
+  static constexpr int kTerms = (BASIS == G3PCF_BASIS_SPIN) ? kTermsSpin
+                                : (BASIS == kBasisDeg)      ? kTermsDeg
+                                                            : kTermsCart;
   // read-only device memory in the constant address space (scalar loads)
   using CoefPtr = const double __attribute__((address_space(4)))*;
 
@@ -731,7 +733,11 @@ struct PairKernel {
         reduce_store(W, ch);
       });
       wave_lds_fence();
-      convert(a, W, b, row);
+      if constexpr (BASIS == kBasisDeg) {
+        store_deg(a, W, b, row);
+      } else {
+        convert(a, W, b, row);
+      }
       wave_lds_fence();
     } else {
       // the shell's coefficients, read through the scalar cache (uniform)
@@ -927,6 +933,15 @@ struct PairKernel {
     }
   }
 
+  // The shell's degenerate-triangle sums D_n, n <= 2 lmax, into the row of the
+  // pair-block (FP64, [shell][n]).
+  static __device__ __forceinline__ void store_deg(const PairArgs& a, const Lds& W, int b,
+                                                   long long row) {
+    const int lane = threadIdx.x % kWave;
+    const int nd = 2 * a.lmax + 1;
+    if (lane < nd) a.A[row * a.lay.W + b * nd + lane] = double(W.M[lane]);
+  }
+
   // Adjoint for one pair per lane: the full polynomial sum_t g_t mono_t(u) in
   // FP64 (its coefficients cancel strongly at l = 10).  The coefficients are
   // the same for every lane, so they are read into scalar registers.
@@ -976,6 +991,11 @@ hipError_t launch_pair_forward(const PairArgs& a, int fp64, int basis, hipStream
                                      : launch_one<double, G3PCF_BASIS_CARTESIAN, false>(a, st);
   return basis == G3PCF_BASIS_SPIN ? launch_one<float, G3PCF_BASIS_SPIN, false>(a, st)
                                    : launch_one<float, G3PCF_BASIS_CARTESIAN, false>(a, st);
+}
+
+hipError_t launch_pair_distinct(const PairArgs& a, int fp64, hipStream_t st) {
+  return fp64 ? launch_one<double, kBasisDeg, false>(a, st)
+              : launch_one<float, kBasisDeg, false>(a, st);
 }
 
 hipError_t launch_pair_adjoint(const PairArgs& a, int fp64, int basis, hipStream_t st) {

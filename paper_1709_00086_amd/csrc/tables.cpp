@@ -151,6 +151,82 @@ void build_conv_table(int basis, ConvTable* t) {
     }
 }
 
+// Degenerate-triangle table.  For one secondary at unit separation u the j = k
+// term of zeta^m_{ll'} is w_i w_j^2 conj(Y_lm(u)) Y_l'm(u) = w_i w_j^2
+// Pbar_lm(u_z) Pbar_l'm(u_z) (the azimuthal factors cancel, Pbar_lm = N_lm P_l^m,
+// the Condon-Shortley signs square to one): a polynomial of degree l + l' in
+// u_z alone, expanded here in Legendre polynomials,
+//   Pbar_lm(z) Pbar_l'm(z) = sum_n G[m][l][l'][n] P_n(z),
+//   G = (2n + 1) / 2 int_{-1}^{1} Pbar_lm Pbar_l'm P_n dz,
+// by Gauss-Legendre quadrature with 32 nodes (exact to degree 63 >= 40).
+namespace {
+
+// P_l^m(z) (Condon-Shortley phase) for m <= l <= kDeg: p[l] for fixed m.
+void assoc_legendre(int m, double z, double* p) {
+  const double s = std::sqrt(std::fmax(0.0, 1.0 - z * z));
+  double pmm = 1.0;
+  for (int k = 1; k <= m; ++k) pmm *= -(2.0 * k - 1.0) * s;
+  for (int l = 0; l <= kDeg; ++l) p[l] = 0.0;
+  p[m] = pmm;
+  if (m + 1 <= kDeg) p[m + 1] = z * (2.0 * m + 1.0) * pmm;
+  for (int l = m + 2; l <= kDeg; ++l)
+    p[l] = ((2.0 * l - 1.0) * z * p[l - 1] - (l + m - 1.0) * p[l - 2]) / double(l - m);
+}
+
+void legendre_all(double z, int nmax, double* p) {  // P_n(z), n <= nmax
+  p[0] = 1.0;
+  if (nmax >= 1) p[1] = z;
+  for (int n = 1; n < nmax; ++n) p[n + 1] = ((2.0 * n + 1.0) * z * p[n] - n * p[n - 1]) / (n + 1.0);
+}
+
+// Gauss-Legendre nodes and weights on [-1, 1]: Newton iteration on P_K from
+// the Chebyshev-like first guesses cos(pi (i + 3/4) / (K + 1/2)).
+void gauss_legendre(int K, double* x, double* w) {
+  std::vector<double> p(K + 1);
+  for (int i = 0; i < K; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (K + 0.5));
+    double dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      legendre_all(z, K, p.data());
+      dp = K * (z * p[K] - p[K - 1]) / (z * z - 1.0);  // P_K'(z)
+      const double dz = p[K] / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    legendre_all(z, K, p.data());
+    dp = K * (z * p[K] - p[K - 1]) / (z * z - 1.0);
+    x[i] = z;
+    w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+}  // namespace
+
+void build_deg_table(double* G) {
+  constexpr int K = 32;
+  double x[K], wq[K];
+  gauss_legendre(K, x, wq);
+  std::memset(G, 0, sizeof(double) * kDegTable);
+  double pl[kDeg + 1], pn[kTermsDeg];
+  for (int m = 0; m <= kDeg; ++m) {
+    for (int q = 0; q < K; ++q) {
+      assoc_legendre(m, x[q], pl);
+      legendre_all(x[q], kTermsDeg - 1, pn);
+      for (int l = m; l <= kDeg; ++l) {
+        const double nl =
+            std::sqrt((2.0 * l + 1.0) / (4.0 * M_PI) * double(fact(l - m)) / double(fact(l + m)));
+        for (int lp = m; lp <= kDeg; ++lp) {
+          const double nlp = std::sqrt((2.0 * lp + 1.0) / (4.0 * M_PI) * double(fact(lp - m)) /
+                                       double(fact(lp + m)));
+          const double f = wq[q] * nl * pl[l] * nlp * pl[lp];
+          for (int n = 0; n <= l + lp; ++n)
+            G[deg_index(m, l, lp, n)] += 0.5 * (2.0 * n + 1.0) * f * pn[n];
+        }
+      }
+    }
+  }
+}
+
 }  // namespace g3
 
 // Host-side evaluation of the library's conversion for one unit vector and

@@ -491,4 +491,126 @@ hipError_t launch_zeta_pairblock(const ZetaArgs& z, hipStream_t st) {
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- degenerate triangles
+// The triangles j = k (the same secondary on both sides, so b1 = b2) are part
+// of the product a_lm conj(a_l'm) (Sec. 3.1).  Without them, zeta^m_{ll'}(b, b)
+// loses sum_i w_i sum_{j in b} w_j^2 conj(Y_lm(u_ij)) Y_l'm(u_ij), which is
+// sum_n G[m][l][l'][n] D(b, n) with D(b, n) = sum_i w_i sum_{j in b} w_j^2 P_n(u_z).
+
+__device__ double g_deg[kDegTable];
+
+namespace {
+
+constexpr int kDegRows = 512;  // rows of a pair-block summed per workgroup
+
+// partial[blk][c] = sum over the workgroup's rows r, in order, of w_r X[r][c]
+// (c < ncols; rows of the pair-block that are not primaries are skipped).
+__global__ __launch_bounds__(256) void k_deg_partial(const double* __restrict__ X, int rowW,
+                                                     int ncols, const double* __restrict__ wsort,
+                                                     const int* __restrict__ plist,
+                                                     const long long* __restrict__ nprim,
+                                                     long long p_begin, long long p_count,
+                                                     double* __restrict__ partial) {
+  const long long valid = min(p_count, (long long)(*nprim) - p_begin);
+  const long long r0 = (long long)blockIdx.x * kDegRows;
+  const long long r1 = min(r0 + kDegRows, valid);
+  for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
+    double s = 0.0;
+    for (long long r = r0; r < r1; ++r) s += wsort[plist[p_begin + r]] * X[r * rowW + c];
+    partial[(long long)blockIdx.x * ncols + c] = s;
+  }
+}
+
+// D[c] += sum over the workgroups, in order, of partial[blk][c]
+__global__ void k_deg_accum(const double* __restrict__ partial, int nblk, int ncols,
+                            double* __restrict__ D) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncols) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += partial[(long long)b * ncols + c];
+  D[c] += s;
+}
+
+__device__ __forceinline__ long long zpos(int lmax, int nb, int m, int l, int lp, int b1,
+                                          int b2) {
+  const int L1 = lmax + 1;
+  return ((((long long)m * L1 + l) * L1 + lp) * nb + b1) * nb + b2;
+}
+
+// Re zeta^m_{ll'}(b, b) -= sum_n G[m][l][l'][n] D[b][n]  (the removed terms are real)
+__global__ void k_deg_apply(const double* __restrict__ D, int lmax, int nb,
+                            double* __restrict__ zeta) {
+  const int L1 = lmax + 1;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)L1 * L1 * L1 * nb) return;
+  const int b = int(idx % nb);
+  long long t = idx / nb;
+  const int lp = int(t % L1);
+  t /= L1;
+  const int l = int(t % L1);
+  const int m = int(t / L1);
+  if (l < m || lp < m) return;
+  const int nd = 2 * lmax + 1;
+  double s = 0.0;
+  for (int n = 0; n <= l + lp; ++n) s += g_deg[deg_index(m, l, lp, n)] * D[b * nd + n];
+  zeta[zpos(lmax, nb, m, l, lp, b, b) * 2] -= s;
+}
+
+// iso[l][b1][b2] = 4 pi / (2l + 1) (zeta^0_ll + 2 sum_{m >= 1} Re zeta^m_ll)(b1, b2)
+__global__ void k_isotropic(const double* __restrict__ zeta, int lmax, int nb,
+                            double* __restrict__ iso) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)(lmax + 1) * nb * nb) return;
+  const int b2 = int(idx % nb);
+  const int b1 = int((idx / nb) % nb);
+  const int l = int(idx / ((long long)nb * nb));
+  double s = 0.0;
+  for (int m = 1; m <= l; ++m) s += zeta[zpos(lmax, nb, m, l, l, b1, b2) * 2];
+  s = zeta[zpos(lmax, nb, 0, l, l, b1, b2) * 2] + 2.0 * s;
+  iso[idx] = 4.0 * M_PI / (2.0 * l + 1.0) * s;
+}
+
+}  // namespace
+
+hipError_t upload_deg_table() {
+  static double host[kDegTable];
+  static bool built = false;
+  if (!built) {
+    build_deg_table(host);
+    built = true;
+  }
+  return hipMemcpyToSymbol(HIP_SYMBOL(g_deg), host, sizeof(host), 0, hipMemcpyHostToDevice);
+}
+
+size_t deg_partial_doubles(long long PB, int nb, int lmax) {
+  return size_t((PB + kDegRows - 1) / kDegRows) * size_t(nb) * size_t(2 * lmax + 1);
+}
+
+hipError_t launch_deg_reduce(const double* X, int rowW, int nb, int lmax, const double* wsort,
+                             const int* plist, const long long* nprim, long long p_begin,
+                             long long p_count, double* partial, double* D, hipStream_t st) {
+  if (p_count <= 0) return hipSuccess;
+  const int ncols = nb * (2 * lmax + 1);
+  const unsigned nblk = unsigned((p_count + kDegRows - 1) / kDegRows);
+  hipLaunchKernelGGL(k_deg_partial, dim3(nblk), dim3(256), 0, st, X, rowW, ncols, wsort, plist,
+                     nprim, p_begin, p_count, partial);
+  hipLaunchKernelGGL(k_deg_accum, dim3((ncols + 255) / 256), dim3(256), 0, st, partial,
+                     int(nblk), ncols, D);
+  return hipGetLastError();
+}
+
+hipError_t launch_deg_apply(const double* D, int lmax, int nb, double* zeta, hipStream_t st) {
+  const long long n = (long long)(lmax + 1) * (lmax + 1) * (lmax + 1) * nb;
+  hipLaunchKernelGGL(k_deg_apply, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, D, lmax,
+                     nb, zeta);
+  return hipGetLastError();
+}
+
+hipError_t launch_isotropic(const double* zeta, int lmax, int nb, double* iso, hipStream_t st) {
+  const long long n = (long long)(lmax + 1) * nb * nb;
+  hipLaunchKernelGGL(k_isotropic, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, zeta, lmax,
+                     nb, iso);
+  return hipGetLastError();
+}
+
 }  // namespace g3

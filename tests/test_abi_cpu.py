@@ -98,6 +98,7 @@ def _problem(**kw):
     p.primary_mask = None
     p.accumulate = kw.get("accumulate", 0)
     p.pairs_out = None
+    p.distinct = kw.get("distinct", 0)
     return p
 
 
@@ -119,6 +120,7 @@ def _problem(**kw):
     dict(zeta_prec=9),
     dict(basis=3),
     dict(accumulate=2),
+    dict(distinct=2),
 ])
 def test_invalid_arguments_are_rejected_before_any_device_work(lib, kw):
     p = _problem(**kw)
@@ -164,3 +166,35 @@ def test_null_pointers_rejected(lib):
     assert lib.g3pcf_workspace_bytes(ctypes.byref(p), 2, ctypes.byref(out)) == _lib.EINVAL
     assert lib.g3pcf_forward(ctypes.byref(p), None, None, 0, None) == _lib.EINVAL
     assert lib.g3pcf_backward(ctypes.byref(p), None, None, None, 0, None) == _lib.EINVAL
+
+
+def test_degenerate_term_reproduces_scipy_ylm_products(lib):
+    """The distinct = 1 correction's Legendre table: conj(Y_lm(u)) Y_l'm(u)."""
+    from scipy.special import sph_harm_y
+    rng = np.random.default_rng(5)
+    lmax = 10
+    for uz in np.concatenate([rng.uniform(-1, 1, 40), [-1.0, 0.0, 1.0]]):
+        got = np.array(_lib.degenerate_term(lmax, uz))
+        th = math.acos(uz)
+        ph = rng.uniform(0, 2 * math.pi)  # the product does not depend on the azimuth
+        Y = np.array([[sph_harm_y(l, m, th, ph) if m <= l else 0.0 for m in range(lmax + 1)]
+                      for l in range(lmax + 1)])
+        ref = np.zeros_like(got)
+        for m in range(lmax + 1):
+            ref[m] = (np.conj(Y[:, m])[:, None] * Y[:, m][None, :]).real
+        assert np.abs(got - ref).max() <= 1e-12
+
+
+def test_distinct_backward_is_unsupported_before_device_work(lib):
+    p = _problem(distinct=1)
+    rc = lib.g3pcf_backward(ctypes.byref(p), ctypes.c_void_p(0x3000), ctypes.c_void_p(0x4000),
+                            ctypes.c_void_p(0x5000), 1 << 30, None)
+    assert rc == _lib.EUNSUPPORTED
+    assert b"distinct" in lib.g3pcf_last_error()
+
+
+@pytest.mark.parametrize("args", [(11, 4), (-1, 4), (4, 0), (4, 33)])
+def test_isotropic_rejects_bad_sizes_before_device_work(lib, args):
+    rc = lib.g3pcf_isotropic(args[0], args[1], ctypes.c_void_p(0x3000), ctypes.c_void_p(0x4000),
+                             None)
+    assert rc == _lib.EINVAL
