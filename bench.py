@@ -81,6 +81,9 @@ def main():
     ap.add_argument("--distinct", action="store_true",
                     help="leave out the degenerate j = k triangles (forward only, so it "
                          "implies --forward-only)")
+    ap.add_argument("--regions", type=int, default=0, metavar="K",
+                    help="partial zeta of K^3 spatial cubes of primaries (jack-knife regions; "
+                         "forward only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--sample", type=int, default=8192,
@@ -89,7 +92,7 @@ def main():
                     help="first run one plain device copy of MIB MiB (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
-    if args.distinct:
+    if args.distinct or args.regions:
         args.forward_only = True
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -127,8 +130,23 @@ def main():
     _, pairs = api.zeta(pos, w, cfg, out=zeta_out, workspace=ws, return_pairs=True)
     log(f"accepted ordered pairs: {pairs} ({pairs / cat.n:.1f} per primary)")
 
+    region = None
+    if args.regions:
+        k = args.regions
+        p64 = np.asarray(cat.pos, dtype=np.float64)
+        cube = np.clip(np.floor((p64 - np.asarray(cat.box_lo)) / np.asarray(cat.box) * k),
+                       0, k - 1).astype(np.int64)
+        region = torch.from_numpy(((cube[:, 0] * k + cube[:, 1]) * k + cube[:, 2])
+                                  .astype(np.int32)).to(dev)
+        zeta_regions_out = torch.empty((k ** 3,) + api.zeta_shape(cat.lmax, cat.nbins),
+                                       dtype=torch.float64, device=dev)
+
     def step(trace=None):
-        api.zeta(pos, w, cfg, out=zeta_out, workspace=ws, trace=trace)
+        if region is not None:
+            api.zeta_regions(pos, w, cfg, region, args.regions ** 3, out=zeta_regions_out,
+                             workspace=ws, trace=trace)
+        else:
+            api.zeta(pos, w, cfg, out=zeta_out, workspace=ws, trace=trace)
         if not args.forward_only:
             api.zeta_backward(pos, w, cfg, c, workspace=ws, trace=trace)
 
@@ -192,6 +210,7 @@ def main():
             "basis": args.basis,
             "step": "forward" if args.forward_only else "forward+backward",
             "distinct": bool(args.distinct),
+            "regions": args.regions ** 3 if args.regions else 0,
             "accepted_pairs": pairs,
         },
         "stage_ms_per_step": stage_ms,

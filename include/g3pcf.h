@@ -176,6 +176,22 @@ int g3pcf_workspace_bytes(const g3pcf_problem* prob, int backward, size_t* bytes
 int g3pcf_forward(const g3pcf_problem* prob, double* zeta, void* ws, size_t ws_bytes,
                   void* stream);
 
+/* Forward pass per region of primaries (the partial zeta of each region, e.g.
+ * for jack-knife resampling: zeta without region r is the full zeta minus
+ * region r's).  region: device [n] int32; galaxy i is a primary of region
+ * region[i] when 0 <= region[i] < nregions (and, if primary_mask is set,
+ * primary_mask[i] != 0); every galaxy is a secondary of every region.
+ * zeta: device [nregions][g3pcf_zeta_len] doubles, region-major, overwritten
+ * (or added into with accumulate = 1).  The cell list is built once; each
+ * region runs its own primary list through the pair stage, so the pair work
+ * is that of one forward pass over all assigned primaries; the call waits for
+ * the stream once per region to read the region's primary count.  ws: at least
+ * g3pcf_workspace_bytes(prob, 0) bytes.  pairs_out (if set): accepted pairs
+ * summed over the regions.  Errors as g3pcf_forward, and G3PCF_EINVAL for
+ * nregions outside 1..2^20 or a NULL region with n > 0. */
+int g3pcf_forward_regions(const g3pcf_problem* prob, const int32_t* region, int nregions,
+                          double* zeta, void* ws, size_t ws_bytes, void* stream);
+
 /* Adjoint pass.  With L = sum over the real view of grad_zeta * zeta
  * (grad_zeta laid out like zeta), stores dL/dw_k for every galaxy k in
  * grad_w [n] (added to it when accumulate = 1).  zeta is linear in the weight

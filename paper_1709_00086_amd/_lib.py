@@ -20,7 +20,8 @@ BASIS_CARTESIAN, BASIS_SPIN = 0, 1
 EXPORTED = ["g3pcf_zeta_len", "g3pcf_num_terms", "g3pcf_workspace_bytes", "g3pcf_forward",
             "g3pcf_backward", "g3pcf_last_error", "g3pcf_conj_ylm_via_monomials",
             "g3pcf_trace_create", "g3pcf_trace_reset", "g3pcf_trace_read",
-            "g3pcf_trace_destroy", "g3pcf_isotropic", "g3pcf_degenerate_term"]
+            "g3pcf_trace_destroy", "g3pcf_isotropic", "g3pcf_degenerate_term",
+            "g3pcf_forward_regions"]
 STAGES = {0: "cells", 1: "pairs", 2: "zeta", 3: "adj_coef", 4: "pair_adjoint", 5: "distinct"}
 
 
@@ -97,6 +98,9 @@ def load():
     lib.g3pcf_trace_read.restype = ctypes.c_int
     lib.g3pcf_trace_destroy.argtypes = [ctypes.c_void_p]
     lib.g3pcf_trace_destroy.restype = None
+    lib.g3pcf_forward_regions.argtypes = [P, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    lib.g3pcf_forward_regions.restype = ctypes.c_int
     lib.g3pcf_isotropic.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_void_p]
     lib.g3pcf_isotropic.restype = ctypes.c_int

@@ -137,6 +137,38 @@ def zeta(pos: torch.Tensor, w: torch.Tensor, cfg: Config,
     return out
 
 
+def zeta_regions(pos: torch.Tensor, w: torch.Tensor, cfg: Config, region: torch.Tensor,
+                 nregions: int, primary_mask: Optional[torch.Tensor] = None,
+                 accumulate: bool = False, out: Optional[torch.Tensor] = None,
+                 workspace: Optional[Workspace] = None, return_pairs: bool = False,
+                 trace: Optional["_lib.Trace"] = None):
+    """Partial zeta of each region of primaries, float64 [nregions][m][l][l'][b1][b2][2].
+
+    ``region`` (int32, device, shape (n,)): galaxy i is a primary of region
+    region[i] when 0 <= region[i] < nregions; every galaxy is a secondary."""
+    import ctypes
+    _require_cuda(region, "region")
+    if region.dtype != torch.int32 or region.shape != (pos.shape[0],) or not region.is_contiguous():
+        raise ValueError("region must be a contiguous int32 tensor of shape (n,)")
+    pairs = ctypes.c_int64(0)
+    p = make_problem(pos, w, cfg, primary_mask, accumulate,
+                     ctypes.pointer(pairs) if return_pairs else None, trace)
+    shape = (nregions,) + zeta_shape(cfg.lmax, cfg.nbins)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float64, device=pos.device)
+    elif out.shape != shape or out.dtype != torch.float64 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float64 tensor of shape " + str(shape))
+    ws = (workspace or _default_ws).get(_lib.workspace_bytes(p, 0), pos.device)
+    stream = torch.cuda.current_stream(pos.device).cuda_stream
+    _lib.check(_lib.load().g3pcf_forward_regions(
+        ctypes.byref(p), ctypes.c_void_p(region.data_ptr() if p.n else 0), int(nregions),
+        ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+        ctypes.c_size_t(ws.numel()), ctypes.c_void_p(stream)))
+    if return_pairs:
+        return out, int(pairs.value)
+    return out
+
+
 def zeta_backward(pos: torch.Tensor, w: torch.Tensor, cfg: Config, grad_zeta: torch.Tensor,
                   primary_mask: Optional[torch.Tensor] = None,
                   workspace: Optional[Workspace] = None,

@@ -207,8 +207,9 @@ int stage_catalogue(const g3pcf_problem& p, const Ws& w, void* ws, hipStream_t s
   Counters* c = at<Counters>(ws, w.counters);
   e = launch_fill_int(reinterpret_cast<int*>(c), sizeof(Counters) / 4, 0, st);
   if (e != hipSuccess) return hip_fail(e, "counters");
-  e = launch_primaries(p.primary_mask, at<int>(ws, w.perm), p.n, at<int>(ws, w.flags),
-                       at<int>(ws, w.plist), &c->nprim, at<void>(ws, w.scan), w.scan_bytes, st);
+  e = launch_primaries(p.primary_mask, nullptr, 0, at<int>(ws, w.perm), p.n,
+                       at<int>(ws, w.flags), at<int>(ws, w.plist), &c->nprim, at<void>(ws, w.scan),
+                       w.scan_bytes, st);
   if (e != hipSuccess) return hip_fail(e, "primary list");
   return G3PCF_OK;
 }
@@ -252,6 +253,80 @@ PairArgs pair_args(const g3pcf_problem& p, const Ws& w, void* ws) {
   a.perm = at<int>(ws, w.perm);
   a.wsort = at<double>(ws, w.wsort);
   return a;
+}
+
+int check_workspace(const Ws& w, void* ws, size_t ws_bytes) {
+  if (!ws || ws_bytes < w.total)
+    return fail(G3PCF_EWORKSPACE, "workspace needs " + std::to_string(w.total) + " bytes");
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign)
+    return fail(G3PCF_EWORKSPACE, "workspace must be 256-byte aligned");
+  return G3PCF_OK;
+}
+
+int forward_tables(const g3pcf_problem& p) {
+  int rc = ensure_tables(p.basis);
+  if (!rc && p.distinct) rc = ensure_tables(kBasisDeg);
+  return rc;
+}
+
+// The pair-blocks of the current primary list (at most `cover` primaries):
+// pair kernel, Gram products into zeta, and (distinct) the degenerate-triangle
+// pass and its correction.
+int forward_pairs(const g3pcf_problem& p, const Ws& w, void* ws, double* zeta, int64_t cover,
+                  hipStream_t st) {
+  hipError_t e;
+  PairArgs a = pair_args(p, w, ws);
+  const int fp64 = (p.pair_prec == G3PCF_PREC_FP64);
+  Counters* c = at<Counters>(ws, w.counters);
+  double* degD = at<double>(ws, w.degD);
+  if (p.distinct &&
+      (e = launch_fill_double(degD, int64_t(p.nbins) * (2 * p.lmax + 1), 0.0, st)) != hipSuccess)
+    return hip_fail(e, "degenerate sums clear");
+  for (int64_t b0 = 0; b0 < cover; b0 += w.PB) {
+    a.p_begin = b0;
+    a.p_count = std::min<int64_t>(w.PB, cover - b0);
+    a.pairs = &c->pairs;
+    {
+      StageScope sc(p.trace, G3PCF_STAGE_PAIRS, st);
+      if ((e = launch_pair_forward(a, fp64, p.basis, st)) != hipSuccess)
+        return hip_fail(e, "pair kernel");
+    }
+    {
+      StageScope scz(p.trace, G3PCF_STAGE_ZETA, st);
+      ZetaArgs z{};
+      z.A = a.A;
+      z.wsort = a.wsort;
+      z.plist = a.plist;
+      z.nprim = &c->nprim;
+      z.row_begin = b0;
+      z.sub_begin = 0;
+      z.K = a.p_count;
+      z.lay = w.lay;
+      z.ops = at<void>(ws, w.ops);
+      z.C32 = at<float>(ws, w.C);
+      z.C64 = at<double>(ws, w.C);
+      z.zeta = zeta;
+      z.prec = p.zeta_prec;
+      if ((e = launch_zeta_pairblock(z, st)) != hipSuccess) return hip_fail(e, "zeta");
+    }
+    if (p.distinct) {
+      // the same pairs again for their sums w_j^2 P_n(u_z), written over the
+      // pair-block's A rows (already reduced into zeta), then summed with w_i
+      StageScope scd(p.trace, G3PCF_STAGE_DISTINCT, st);
+      a.pairs = &c->pairs_deg;
+      if ((e = launch_pair_distinct(a, fp64, st)) != hipSuccess)
+        return hip_fail(e, "degenerate-triangle pass");
+      if ((e = launch_deg_reduce(a.A, w.lay.W, p.nbins, p.lmax, a.wsort, a.plist, &c->nprim, b0,
+                                 a.p_count, at<double>(ws, w.degP), degD, st)) != hipSuccess)
+        return hip_fail(e, "degenerate-triangle sums");
+    }
+  }
+  if (p.distinct) {
+    StageScope scd(p.trace, G3PCF_STAGE_DISTINCT, st);
+    if ((e = launch_deg_apply(degD, p.lmax, p.nbins, zeta, st)) != hipSuccess)
+      return hip_fail(e, "degenerate-triangle correction");
+  }
+  return G3PCF_OK;
 }
 
 int finish_pairs(const g3pcf_problem& p, const Ws& w, void* ws, hipStream_t st) {
@@ -349,13 +424,9 @@ int g3pcf_forward(const g3pcf_problem* prob, double* zeta, void* ws, size_t ws_b
   if (!zeta) return fail(G3PCF_EINVAL, "zeta is NULL");
   const g3pcf_problem& p = *prob;
   const Ws w = plan(p, 0);
-  if (!ws || ws_bytes < w.total)
-    return fail(G3PCF_EWORKSPACE, "workspace needs " + std::to_string(w.total) + " bytes");
-  if (reinterpret_cast<uintptr_t>(ws) % kAlign)
-    return fail(G3PCF_EWORKSPACE, "workspace must be 256-byte aligned");
+  if ((rc = check_workspace(w, ws, ws_bytes))) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if ((rc = ensure_tables(p.basis))) return rc;
-  if (p.distinct && (rc = ensure_tables(kBasisDeg))) return rc;
+  if ((rc = forward_tables(p))) return rc;
   const size_t zlen = g3pcf_zeta_len(p.lmax, p.nbins);
   hipError_t e;
   if (!p.accumulate && (e = launch_fill_double(zeta, int64_t(zlen), 0.0, st)) != hipSuccess)
@@ -368,56 +439,53 @@ int g3pcf_forward(const g3pcf_problem* prob, double* zeta, void* ws, size_t ws_b
     StageScope sc(p.trace, G3PCF_STAGE_CELLS, st);
     if ((rc = stage_catalogue(p, w, ws, st))) return rc;
   }
-  PairArgs a = pair_args(p, w, ws);
-  const int fp64 = (p.pair_prec == G3PCF_PREC_FP64);
-  Counters* c = at<Counters>(ws, w.counters);
-  double* degD = at<double>(ws, w.degD);
-  if (p.distinct &&
-      (e = launch_fill_double(degD, int64_t(p.nbins) * (2 * p.lmax + 1), 0.0, st)) != hipSuccess)
-    return hip_fail(e, "degenerate sums clear");
-  for (int64_t b0 = 0; b0 < p.n; b0 += w.PB) {
-    a.p_begin = b0;
-    a.p_count = std::min<int64_t>(w.PB, p.n - b0);
-    a.pairs = &c->pairs;
-    {
-      StageScope sc(p.trace, G3PCF_STAGE_PAIRS, st);
-      if ((e = launch_pair_forward(a, fp64, p.basis, st)) != hipSuccess)
-        return hip_fail(e, "pair kernel");
-    }
-    {
-      StageScope scz(p.trace, G3PCF_STAGE_ZETA, st);
-      ZetaArgs z{};
-      z.A = a.A;
-      z.wsort = a.wsort;
-      z.plist = a.plist;
-      z.nprim = &c->nprim;
-      z.row_begin = b0;
-      z.sub_begin = 0;
-      z.K = a.p_count;
-      z.lay = w.lay;
-      z.ops = at<void>(ws, w.ops);
-      z.C32 = at<float>(ws, w.C);
-      z.C64 = at<double>(ws, w.C);
-      z.zeta = zeta;
-      z.prec = p.zeta_prec;
-      if ((e = launch_zeta_pairblock(z, st)) != hipSuccess) return hip_fail(e, "zeta");
-    }
-    if (p.distinct) {
-      // the same pairs again for their sums w_j^2 P_n(u_z), written over the
-      // pair-block's A rows (already reduced into zeta), then summed with w_i
-      StageScope scd(p.trace, G3PCF_STAGE_DISTINCT, st);
-      a.pairs = &c->pairs_deg;
-      if ((e = launch_pair_distinct(a, fp64, st)) != hipSuccess)
-        return hip_fail(e, "degenerate-triangle pass");
-      if ((e = launch_deg_reduce(a.A, w.lay.W, p.nbins, p.lmax, a.wsort, a.plist, &c->nprim, b0,
-                                 a.p_count, at<double>(ws, w.degP), degD, st)) != hipSuccess)
-        return hip_fail(e, "degenerate-triangle sums");
-    }
+  if ((rc = forward_pairs(p, w, ws, zeta, p.n, st))) return rc;
+  return finish_pairs(p, w, ws, st);
+}
+
+int g3pcf_forward_regions(const g3pcf_problem* prob, const int32_t* region, int nregions,
+                          double* zeta, void* ws, size_t ws_bytes, void* stream) {
+  int rc = validate(prob);
+  if (rc) return rc;
+  if (nregions < 1 || nregions > (1 << 20)) return fail(G3PCF_EINVAL, "nregions must be 1..2^20");
+  if (!zeta) return fail(G3PCF_EINVAL, "zeta is NULL");
+  if (!region && prob->n > 0) return fail(G3PCF_EINVAL, "region is NULL");
+  const g3pcf_problem& p = *prob;
+  const Ws w = plan(p, 0);
+  if ((rc = check_workspace(w, ws, ws_bytes))) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((rc = forward_tables(p))) return rc;
+  const size_t zlen = g3pcf_zeta_len(p.lmax, p.nbins);
+  hipError_t e;
+  if (!p.accumulate &&
+      (e = launch_fill_double(zeta, int64_t(zlen) * nregions, 0.0, st)) != hipSuccess)
+    return hip_fail(e, "zeta clear");
+  if (p.n == 0) {
+    if (p.pairs_out) *p.pairs_out = 0;
+    return G3PCF_OK;
   }
-  if (p.distinct) {
-    StageScope scd(p.trace, G3PCF_STAGE_DISTINCT, st);
-    if ((e = launch_deg_apply(degD, p.lmax, p.nbins, zeta, st)) != hipSuccess)
-      return hip_fail(e, "degenerate-triangle correction");
+  {
+    StageScope sc(p.trace, G3PCF_STAGE_CELLS, st);
+    if ((rc = stage_catalogue(p, w, ws, st))) return rc;
+  }
+  // one cell list; per region its own primary list and pair-blocks, sized by
+  // the region's primary count (read back: one wait per region)
+  Counters* c = at<Counters>(ws, w.counters);
+  for (int r = 0; r < nregions; ++r) {
+    long long count = 0;
+    {
+      StageScope sc(p.trace, G3PCF_STAGE_CELLS, st);
+      if ((e = launch_primaries(p.primary_mask, region, r, at<int>(ws, w.perm), p.n,
+                                at<int>(ws, w.flags), at<int>(ws, w.plist), &c->nprim,
+                                at<void>(ws, w.scan), w.scan_bytes, st)) != hipSuccess)
+        return hip_fail(e, "region primary list");
+    }
+    if ((e = hipMemcpyAsync(&count, &c->nprim, sizeof(count), hipMemcpyDeviceToHost, st)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+      return hip_fail(e, "region primary count");
+    if (count > 0 && (rc = forward_pairs(p, w, ws, zeta + zlen * size_t(r), count, st)))
+      return rc;
   }
   return finish_pairs(p, w, ws, st);
 }

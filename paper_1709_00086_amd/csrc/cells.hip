@@ -120,15 +120,20 @@ __global__ void k_cell_order(const V4* __restrict__ in4, const int* __restrict__
   }
 }
 
-__global__ void k_primary_flags(const uint8_t* __restrict__ mask, const int* __restrict__ perm,
-                                int64_t n, int* __restrict__ flags) {
+// primary flag of the galaxy in cell-order slot s: in the mask (if any) and,
+// when region ids are given, in region r
+__global__ void k_primary_flags(const uint8_t* __restrict__ mask,
+                                const int32_t* __restrict__ region, int r,
+                                const int* __restrict__ perm, int64_t n,
+                                int* __restrict__ flags) {
   const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (s > n) return;
   if (s == n) {
     flags[s] = 0;
     return;
   }
-  flags[s] = (mask == nullptr || mask[perm[s]] != 0) ? 1 : 0;
+  const int i = perm[s];
+  flags[s] = ((mask == nullptr || mask[i] != 0) && (region == nullptr || region[i] == r)) ? 1 : 0;
 }
 
 __global__ void k_primary_list(const int* __restrict__ flags, const int* __restrict__ pos,
@@ -333,11 +338,12 @@ hipError_t launch_cells(const g3pcf_problem& p, const Grid& g, void* pos4, int* 
   return hipGetLastError();
 }
 
-hipError_t launch_primaries(const uint8_t* mask, const int* perm, int64_t n, int* flags,
-                            int* plist, long long* nprim, void* scan_tmp,
-                            size_t scan_tmp_bytes_, hipStream_t st) {
+hipError_t launch_primaries(const uint8_t* mask, const int32_t* region, int r, const int* perm,
+                            int64_t n, int* flags, int* plist, long long* nprim,
+                            void* scan_tmp, size_t scan_tmp_bytes_, hipStream_t st) {
   const unsigned nb = blocks_for(n + 1, 256);
-  hipLaunchKernelGGL(k_primary_flags, dim3(nb), dim3(256), 0, st, mask, perm, n, flags);
+  hipLaunchKernelGGL(k_primary_flags, dim3(nb), dim3(256), 0, st, mask, region, r, perm, n,
+                     flags);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   // positions: exclusive scan into flags + (n + 1)

@@ -135,9 +135,11 @@ hipError_t launch_cells(const g3pcf_problem& p, const Grid& g, void* pos4, int* 
                         int* cell_count, int* cid, int* perm, double* wsort, void* tmp4,
                         int* tmp_perm, double* tmp_w, void* scan_tmp, size_t scan_tmp_bytes,
                         int fp64, hipStream_t st);
-hipError_t launch_primaries(const uint8_t* mask, const int* perm, int64_t n, int* flags,
-                            int* plist, long long* nprim, void* scan_tmp,
-                            size_t scan_tmp_bytes, hipStream_t st);
+// Primary list (cell order): galaxies in the mask (NULL: all) and, if region
+// is not NULL, with region[i] == r.
+hipError_t launch_primaries(const uint8_t* mask, const int32_t* region, int r, const int* perm,
+                            int64_t n, int* flags, int* plist, long long* nprim,
+                            void* scan_tmp, size_t scan_tmp_bytes, hipStream_t st);
 hipError_t launch_fill_int(int* p, int64_t count, int value, hipStream_t st);
 hipError_t launch_fill_double(double* p, int64_t count, double value, hipStream_t st);
 hipError_t launch_pair_forward(const PairArgs& a, int fp64, int basis, hipStream_t st);

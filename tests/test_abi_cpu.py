@@ -198,3 +198,11 @@ def test_isotropic_rejects_bad_sizes_before_device_work(lib, args):
     rc = lib.g3pcf_isotropic(args[0], args[1], ctypes.c_void_p(0x3000), ctypes.c_void_p(0x4000),
                              None)
     assert rc == _lib.EINVAL
+
+
+@pytest.mark.parametrize("nregions,region", [(0, 0x3000), (1 << 21, 0x3000), (4, None)])
+def test_regions_reject_bad_arguments_before_device_work(lib, nregions, region):
+    p = _problem()
+    rc = lib.g3pcf_forward_regions(ctypes.byref(p), ctypes.c_void_p(region) if region else None,
+                                   nregions, ctypes.c_void_p(0x4000), None, 0, None)
+    assert rc == _lib.EINVAL
