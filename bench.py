@@ -84,6 +84,9 @@ def main():
     ap.add_argument("--regions", type=int, default=0, metavar="K",
                     help="partial zeta of K^3 spatial cubes of primaries (jack-knife regions; "
                          "forward only)")
+    ap.add_argument("--recompute", action="store_true",
+                    help="backward recomputes the a_lm on the pair kernel instead of reading "
+                         "the a_lm store the forward filled")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--sample", type=int, default=8192,
@@ -141,14 +144,21 @@ def main():
         zeta_regions_out = torch.empty((k ** 3,) + api.zeta_shape(cat.lmax, cat.nbins),
                                        dtype=torch.float64, device=dev)
 
+    # the a_lm store (one row per primary, kept from the forward for the
+    # backward; allocated once like the workspace, rewritten by every forward)
+    store = None
+    if not args.forward_only and not args.recompute:
+        store = api.alm_store(pos, w, cfg)
+        log(f"a_lm store: {store.numel() / 1e9:.2f} GB")
+
     def step(trace=None):
         if region is not None:
             api.zeta_regions(pos, w, cfg, region, args.regions ** 3, out=zeta_regions_out,
                              workspace=ws, trace=trace)
         else:
-            api.zeta(pos, w, cfg, out=zeta_out, workspace=ws, trace=trace)
+            api.zeta(pos, w, cfg, out=zeta_out, workspace=ws, trace=trace, alm=store)
         if not args.forward_only:
-            api.zeta_backward(pos, w, cfg, c, workspace=ws, trace=trace)
+            api.zeta_backward(pos, w, cfg, c, workspace=ws, trace=trace, alm=store)
 
     for _ in range(args.warmup):
         step()
@@ -168,8 +178,9 @@ def main():
         stage_ms[name] = stage_ms.get(name, 0.0) + ms
     stage_ms = {k: v / args.steps for k, v in stage_ms.items()}
     pair_launches = [ms for name, ms in recs if name == "pairs"]
-    # forward pair kernel launches in one step (the backward recomputes them)
-    per_step_pair_passes = 1 if args.forward_only else 2
+    # forward pair kernel passes in one step (a backward without the store
+    # recomputes the a_lm on it)
+    per_step_pair_passes = 2 if (not args.forward_only and store is None) else 1
     pair_ms_total = sum(pair_launches) / args.steps
     avg_launch_ms = sum(pair_launches) / max(1, len(pair_launches))
     launches_per_pass = len(pair_launches) / (args.steps * per_step_pair_passes)
@@ -209,6 +220,8 @@ def main():
             "precision": args.precision,
             "basis": args.basis,
             "step": "forward" if args.forward_only else "forward+backward",
+            "backward_alm": None if args.forward_only else ("recomputed" if store is None
+                                                            else "kept from the forward"),
             "distinct": bool(args.distinct),
             "regions": args.regions ** 3 if args.regions else 0,
             "accepted_pairs": pairs,

@@ -127,6 +127,22 @@ typedef struct {
                               conj(Y_lm(u_ij)) Y_l'm(u_ij) at b1 = b2 = b_ij
                               (a second pass over the pairs; forward only:
                               g3pcf_backward returns G3PCF_EUNSUPPORTED)     */
+  void* alm;               /* DEVICE buffer or NULL: the a_lm store, i.e. the
+                              forward pass's a_lm kept for the backward pass (the
+                              adjoint's secondary and primary terms are built from
+                              them, Sec. 3.1).  At least g3pcf_alm_bytes bytes,
+                              256-byte aligned, owned by the caller.
+                              g3pcf_forward: fills it (a fingerprint of the inputs
+                              and one FP64 row of every primary's a_lm(b), in the
+                              library's own order); distinct = 1 is rejected.
+                              g3pcf_backward: reads the a_lm from it instead of
+                              recomputing them on the pair kernel.  If the store
+                              was written for other positions, weights, primary
+                              mask or settings (anything but zeta_prec,
+                              accumulate and the output pointers), the backward
+                              pass fills grad_w with NaN (checked on the device).
+                              g3pcf_forward_regions: must be NULL.               */
+  size_t alm_bytes;        /* size of the alm buffer in bytes                    */
 } g3pcf_problem;
 
 /* Trace with room for `capacity` stage records (2 * capacity HIP events on the
@@ -165,6 +181,12 @@ int g3pcf_num_terms(int basis);
  * the size in *bytes, or a negative status. */
 int g3pcf_workspace_bytes(const g3pcf_problem* prob, int backward, size_t* bytes);
 
+/* Bytes of the a_lm store (problem field alm): 256 + n * W * 8 with
+ * W = nbins (lmax+1)^2 doubles per primary (Re a_lm(b) for 0 <= m <= l <= lmax
+ * and Im a_lm(b) for m >= 1), e.g. 10.2 GB for n = 2^20, lmax = 10, 10 shells.  Returns G3PCF_OK and stores the size in
+ * *bytes, or a negative status. */
+int g3pcf_alm_bytes(const g3pcf_problem* prob, size_t* bytes);
+
 /* Forward pass.  zeta: [g3pcf_zeta_len] doubles (device).  ws: device
  * workspace of at least g3pcf_workspace_bytes(prob, 0) bytes, 256-byte aligned.
  * Steps: wrap positions and build a cell list (counting sort); for every
@@ -201,9 +223,11 @@ int g3pcf_forward_regions(const g3pcf_problem* prob, const int32_t* region, int 
  * with G = grad_re + i grad_im and H_lm(b) = U_lm(b) + conj(V_lm(b)),
  *   U_lm(b)  = sum_{l',b2} conj(G^m_{ll'}(b, b2)) conj(a_l'm(b2)),
  *   V_l'm(b) = sum_{l,b1}  conj(G^m_{ll'}(b1, b)) a_lm(b1).
- * The a_lm are recomputed from the pairs, not stored by the forward pass.
- * Position gradients are not provided.  ws: at least
- * g3pcf_workspace_bytes(prob, 1) bytes.  Same errors as g3pcf_forward. */
+ * The a_lm are recomputed from the pairs on the pair kernel, or, when
+ * prob->alm is set, read from the store g3pcf_forward filled (see the alm
+ * field).  Position gradients are not provided.  ws: at least
+ * g3pcf_workspace_bytes(prob, 1) bytes.  pairs_out (if set): the pairs the
+ * adjoint pass visited.  Same errors as g3pcf_forward. */
 int g3pcf_backward(const g3pcf_problem* prob, const double* grad_zeta, double* grad_w,
                    void* ws, size_t ws_bytes, void* stream);
 

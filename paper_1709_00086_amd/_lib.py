@@ -21,7 +21,7 @@ EXPORTED = ["g3pcf_zeta_len", "g3pcf_num_terms", "g3pcf_workspace_bytes", "g3pcf
             "g3pcf_backward", "g3pcf_last_error", "g3pcf_conj_ylm_via_monomials",
             "g3pcf_trace_create", "g3pcf_trace_reset", "g3pcf_trace_read",
             "g3pcf_trace_destroy", "g3pcf_isotropic", "g3pcf_degenerate_term",
-            "g3pcf_forward_regions"]
+            "g3pcf_forward_regions", "g3pcf_alm_bytes"]
 STAGES = {0: "cells", 1: "pairs", 2: "zeta", 3: "adj_coef", 4: "pair_adjoint", 5: "distinct"}
 
 
@@ -47,6 +47,8 @@ class Problem(ctypes.Structure):
         ("pairs_out", ctypes.POINTER(ctypes.c_int64)),
         ("trace", ctypes.c_void_p),
         ("distinct", ctypes.c_int),
+        ("alm", ctypes.c_void_p),
+        ("alm_bytes", ctypes.c_size_t),
     ]
 
 
@@ -76,6 +78,8 @@ def load():
     lib.g3pcf_num_terms.restype = ctypes.c_int
     lib.g3pcf_workspace_bytes.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
     lib.g3pcf_workspace_bytes.restype = ctypes.c_int
+    lib.g3pcf_alm_bytes.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
+    lib.g3pcf_alm_bytes.restype = ctypes.c_int
     lib.g3pcf_forward.argtypes = [P, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                   ctypes.c_void_p]
     lib.g3pcf_forward.restype = ctypes.c_int
@@ -128,6 +132,12 @@ def num_terms(basis: int) -> int:
 def workspace_bytes(prob: Problem, backward: int) -> int:
     out = ctypes.c_size_t(0)
     check(load().g3pcf_workspace_bytes(ctypes.byref(prob), int(backward), ctypes.byref(out)))
+    return int(out.value)
+
+
+def alm_bytes(prob: Problem) -> int:
+    out = ctypes.c_size_t(0)
+    check(load().g3pcf_alm_bytes(ctypes.byref(prob), ctypes.byref(out)))
     return int(out.value)
 
 

@@ -57,7 +57,8 @@ def _require_cuda(t: torch.Tensor, name: str):
 
 def make_problem(pos: torch.Tensor, w: torch.Tensor, cfg: Config,
                  primary_mask: Optional[torch.Tensor] = None, accumulate: bool = False,
-                 pairs_out=None, trace: Optional["_lib.Trace"] = None) -> _lib.Problem:
+                 pairs_out=None, trace: Optional["_lib.Trace"] = None,
+                 alm: Optional[torch.Tensor] = None) -> _lib.Problem:
     _require_cuda(pos, "pos")
     _require_cuda(w, "w")
     if pos.dim() != 2 or pos.shape[1] != 3:
@@ -96,7 +97,27 @@ def make_problem(pos: torch.Tensor, w: torch.Tensor, cfg: Config,
     p.pairs_out = pairs_out
     p.trace = trace.handle if trace is not None else None
     p.distinct = 1 if cfg.distinct else 0
+    if alm is not None:
+        _require_cuda(alm, "alm")
+        if alm.dtype != torch.uint8 or alm.dim() != 1 or not alm.is_contiguous():
+            raise ValueError("alm must be a contiguous 1-d uint8 tensor (see alm_store)")
+        p.alm = alm.data_ptr()
+        p.alm_bytes = alm.numel()
+    else:
+        p.alm = None
+        p.alm_bytes = 0
     return p
+
+
+def alm_store(pos: torch.Tensor, w: torch.Tensor, cfg: Config) -> torch.Tensor:
+    """An uninitialised a_lm store for (pos, w, cfg): a device uint8 tensor of
+    g3pcf_alm_bytes bytes (n * nbins * (lmax+1)^2 doubles and a header).
+
+    Pass it as ``alm=`` to :func:`zeta`, which fills it, and then to
+    :func:`zeta_backward` with the same inputs, which reads the a_lm from it
+    instead of recomputing them (a mismatch gives a NaN gradient)."""
+    nbytes = _lib.alm_bytes(make_problem(pos, w, cfg))
+    return torch.empty(nbytes, dtype=torch.uint8, device=pos.device)
 
 
 class Workspace:
@@ -118,12 +139,15 @@ _default_ws = Workspace()
 def zeta(pos: torch.Tensor, w: torch.Tensor, cfg: Config,
          primary_mask: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
          accumulate: bool = False, workspace: Optional[Workspace] = None,
-         return_pairs: bool = False, trace: Optional["_lib.Trace"] = None):
-    """zeta^m_{l l'}(b1, b2) as a float64 device tensor [m][l][l'][b1][b2][re, im]."""
+         return_pairs: bool = False, trace: Optional["_lib.Trace"] = None,
+         alm: Optional[torch.Tensor] = None):
+    """zeta^m_{l l'}(b1, b2) as a float64 device tensor [m][l][l'][b1][b2][re, im].
+
+    alm: an a_lm store (:func:`alm_store`) to keep the a_lm in for the backward pass."""
     import ctypes
     pairs = ctypes.c_int64(0)
     p = make_problem(pos, w, cfg, primary_mask, accumulate,
-                     ctypes.pointer(pairs) if return_pairs else None, trace)
+                     ctypes.pointer(pairs) if return_pairs else None, trace, alm)
     shape = zeta_shape(cfg.lmax, cfg.nbins)
     if out is None:
         out = torch.empty(shape, dtype=torch.float64, device=pos.device)
@@ -172,9 +196,13 @@ def zeta_regions(pos: torch.Tensor, w: torch.Tensor, cfg: Config, region: torch.
 def zeta_backward(pos: torch.Tensor, w: torch.Tensor, cfg: Config, grad_zeta: torch.Tensor,
                   primary_mask: Optional[torch.Tensor] = None,
                   workspace: Optional[Workspace] = None,
-                  trace: Optional["_lib.Trace"] = None) -> torch.Tensor:
-    """d(sum grad_zeta * zeta)/dw as a float64 device tensor (n,)."""
-    p = make_problem(pos, w, cfg, primary_mask, trace=trace)
+                  trace: Optional["_lib.Trace"] = None,
+                  alm: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """d(sum grad_zeta * zeta)/dw as a float64 device tensor (n,).
+
+    alm: the a_lm store a :func:`zeta` call over the same inputs filled; the
+    a_lm are then read from it instead of recomputed on the pair kernel."""
+    p = make_problem(pos, w, cfg, primary_mask, trace=trace, alm=alm)
     shape = zeta_shape(cfg.lmax, cfg.nbins)
     gz = grad_zeta.to(torch.float64).contiguous()
     if gz.shape != shape:
@@ -204,29 +232,47 @@ def isotropic(zeta_t: torch.Tensor, lmax: int, nbins: int) -> torch.Tensor:
     return out
 
 
+def _keep_alm(pos: torch.Tensor, w: torch.Tensor, cfg: Config, keep) -> Optional[torch.Tensor]:
+    """The a_lm store for an autograd forward: always (keep=True), never
+    (False), or (None) when it takes at most a quarter of the free device memory."""
+    if keep is False or cfg.distinct:
+        return None
+    nbytes = _lib.alm_bytes(make_problem(pos, w, cfg))
+    if keep is None:
+        free, _ = torch.cuda.mem_get_info(pos.device)
+        if nbytes > free // 4:
+            return None
+    return torch.empty(nbytes, dtype=torch.uint8, device=pos.device)
+
+
 class G3PCF(torch.autograd.Function):
     """zeta as a differentiable function of the weights.
 
-    forward(w, pos, cfg, primary_mask) -> zeta.  Only ``pos``, ``w`` and the
-    mask are saved; the backward pass recomputes the a_lm on the pair kernel.
-    Position gradients are not provided (None).
+    forward(w, pos, cfg, primary_mask, keep_alm) -> zeta.  Saves ``pos``, ``w``,
+    the mask and, unless keep_alm is False (or it would not fit, keep_alm None),
+    the a_lm store, so that the backward pass does not recompute the a_lm on the
+    pair kernel.  Position gradients are not provided (None).
     """
 
     @staticmethod
-    def forward(ctx, w, pos, cfg: Config, primary_mask=None):
+    def forward(ctx, w, pos, cfg: Config, primary_mask=None, keep_alm=None):
         ctx.cfg = cfg
         ctx.save_for_backward(w, pos, primary_mask if primary_mask is not None else
                               torch.empty(0, dtype=torch.uint8, device=pos.device))
         ctx.has_mask = primary_mask is not None
-        return zeta(pos, w.detach(), cfg, primary_mask)
+        wd = w.detach()
+        ctx.alm = _keep_alm(pos, wd, cfg, keep_alm)
+        return zeta(pos, wd, cfg, primary_mask, alm=ctx.alm)
 
     @staticmethod
     def backward(ctx, grad_out):
         w, pos, mask = ctx.saved_tensors
         gw = zeta_backward(pos, w.detach(), ctx.cfg, grad_out,
-                           mask if ctx.has_mask else None)
-        return gw, None, None, None
+                           mask if ctx.has_mask else None, alm=ctx.alm)
+        ctx.alm = None
+        return gw, None, None, None, None
 
 
-def zeta_autograd(w, pos, cfg: Config, primary_mask=None):
-    return G3PCF.apply(w, pos, cfg, primary_mask)
+def zeta_autograd(w, pos, cfg: Config, primary_mask=None, keep_alm=None):
+    """zeta through torch.autograd; keep_alm as in :class:`G3PCF`."""
+    return G3PCF.apply(w, pos, cfg, primary_mask, keep_alm)

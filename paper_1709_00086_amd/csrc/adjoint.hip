@@ -238,11 +238,15 @@ __global__ __launch_bounds__(kFinThreads) void k_adj_finish(AdjArgs a, AdjDims d
 
 __global__ void k_unpermute(const double* __restrict__ gs, const float* __restrict__ gs32,
                             const int* __restrict__ perm, int64_t n, int accumulate,
+                            const unsigned long long* __restrict__ fp_saved,
+                            const unsigned long long* __restrict__ fp_now,
                             double* __restrict__ grad) {
   const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (s >= n) return;
   const int i = perm[s];
-  const double g = gs32 ? gs[s] + double(gs32[s]) : gs[s];
+  double g = gs32 ? gs[s] + double(gs32[s]) : gs[s];
+  // a_lm kept from a forward pass over other inputs: no valid gradient
+  if (fp_saved && *fp_saved != *fp_now) g = __builtin_nan("");
   grad[i] = accumulate ? grad[i] + g : g;
 }
 
@@ -272,10 +276,11 @@ hipError_t launch_adj_coef(const AdjArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_unpermute(const double* gs, const float* gs32, const int* perm, int64_t n,
-                            int accumulate, double* grad, hipStream_t st) {
+                            int accumulate, const unsigned long long* fp_saved,
+                            const unsigned long long* fp_now, double* grad, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_unpermute, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, gs, gs32,
-                     perm, n, accumulate, grad);
+                     perm, n, accumulate, fp_saved, fp_now, grad);
   return hipGetLastError();
 }
 

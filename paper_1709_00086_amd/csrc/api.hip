@@ -190,7 +190,8 @@ struct Counters {
   unsigned long long pairs;
   unsigned long long pairs_adj;
   unsigned long long pairs_deg;  // counted again by the degenerate-triangle pass
-  int pad[8];
+  unsigned long long inputs_hash;  // backward: fingerprint of its inputs (a_lm store check)
+  int pad[6];
   int queue[kQueues * kQueueStride];  // one primary counter per XCD, 64 B apart
 };
 static_assert(sizeof(Counters) <= kCountersBytes, "counters block");
@@ -263,6 +264,73 @@ int check_workspace(const Ws& w, void* ws, size_t ws_bytes) {
   return G3PCF_OK;
 }
 
+// The a_lm store: a 256-byte header (the fingerprint of the forward pass's
+// inputs) and then one row of W doubles per primary in primary-list order.
+constexpr size_t kAlmHeader = 256;
+
+size_t alm_total(const g3pcf_problem& p, const RowLayout& lay) {
+  return kAlmHeader + size_t(p.n) * size_t(lay.W) * 8;
+}
+
+int check_alm(const g3pcf_problem& p, const Ws& w) {
+  if (!p.alm) return G3PCF_OK;
+  const size_t need = alm_total(p, w.lay);
+  if (p.alm_bytes < need)
+    return fail(G3PCF_EWORKSPACE, "alm store needs " + std::to_string(need) + " bytes");
+  if (reinterpret_cast<uintptr_t>(p.alm) % kAlign)
+    return fail(G3PCF_EWORKSPACE, "alm store must be 256-byte aligned");
+  return G3PCF_OK;
+}
+
+double* alm_rows(const g3pcf_problem& p) {
+  return reinterpret_cast<double*>(static_cast<char*>(p.alm) + kAlmHeader);
+}
+
+// splitmix64 output function (Steele, Lea and Flood, OOPSLA 2014), host side
+uint64_t hmix(uint64_t x) {
+  x ^= x >> 30;
+  x *= 0xbf58476d1ce4e5b9ull;
+  x ^= x >> 27;
+  x *= 0x94d049bb133111ebull;
+  return x ^ (x >> 31);
+}
+
+// Hash of the settings that change the a_lm rows (zeta_prec, accumulate and
+// the output pointers do not).
+uint64_t settings_seed(const g3pcf_problem& p) {
+  uint64_t h = hmix(0x6733706366ull + uint64_t(p.n));
+  auto put_d = [&](double v) {
+    uint64_t b;
+    std::memcpy(&b, &v, 8);
+    h = hmix(h ^ b);
+  };
+  auto put_i = [&](int64_t v) { h = hmix(h ^ uint64_t(v)); };
+  for (int k = 0; k < 3; ++k) {
+    put_d(p.box[k]);
+    put_d(p.box_lo[k]);
+    put_d(p.los == G3PCF_LOS_OBSERVER ? p.observer[k] : 0.0);
+  }
+  put_d(p.rmax);
+  put_i(p.periodic);
+  put_i(p.nbins);
+  put_i(p.lmax);
+  put_i(p.los);
+  put_i(p.pair_prec);
+  put_i(p.basis);
+  put_i(p.pos_dtype);
+  return h;
+}
+
+hipError_t fingerprint(const g3pcf_problem& p, const Ws& w, void* ws, unsigned long long* out,
+                       hipStream_t st) {
+  hipError_t e = launch_fill_int(reinterpret_cast<int*>(out), 2, 0, st);
+  if (e != hipSuccess) return e;
+  Counters* c = at<Counters>(ws, w.counters);
+  return launch_fingerprint(at<void>(ws, w.pos4), p.pair_prec == G3PCF_PREC_FP64,
+                            at<double>(ws, w.wsort), at<int>(ws, w.perm), at<int>(ws, w.plist),
+                            &c->nprim, p.n, settings_seed(p), out, st);
+}
+
 int forward_tables(const g3pcf_problem& p) {
   int rc = ensure_tables(p.basis);
   if (!rc && p.distinct) rc = ensure_tables(kBasisDeg);
@@ -271,9 +339,10 @@ int forward_tables(const g3pcf_problem& p) {
 
 // The pair-blocks of the current primary list (at most `cover` primaries):
 // pair kernel, Gram products into zeta, and (distinct) the degenerate-triangle
-// pass and its correction.
+// pass and its correction.  rows: where the a_lm rows go (NULL: the
+// workspace's pair-block rows; else rows of every primary, kept).
 int forward_pairs(const g3pcf_problem& p, const Ws& w, void* ws, double* zeta, int64_t cover,
-                  hipStream_t st) {
+                  double* rows, hipStream_t st) {
   hipError_t e;
   PairArgs a = pair_args(p, w, ws);
   const int fp64 = (p.pair_prec == G3PCF_PREC_FP64);
@@ -286,6 +355,7 @@ int forward_pairs(const g3pcf_problem& p, const Ws& w, void* ws, double* zeta, i
     a.p_begin = b0;
     a.p_count = std::min<int64_t>(w.PB, cover - b0);
     a.pairs = &c->pairs;
+    if (rows) a.A = rows + size_t(b0) * w.lay.W;
     {
       StageScope sc(p.trace, G3PCF_STAGE_PAIRS, st);
       if ((e = launch_pair_forward(a, fp64, p.basis, st)) != hipSuccess)
@@ -329,10 +399,13 @@ int forward_pairs(const g3pcf_problem& p, const Ws& w, void* ws, double* zeta, i
   return G3PCF_OK;
 }
 
-int finish_pairs(const g3pcf_problem& p, const Ws& w, void* ws, hipStream_t st) {
+// pairs_out from the forward count (or, adj = true, the adjoint pass's count)
+int finish_pairs(const g3pcf_problem& p, const Ws& w, void* ws, hipStream_t st,
+                 bool adj = false) {
   if (!p.pairs_out) return G3PCF_OK;
   unsigned long long host = 0;
-  hipError_t e = hipMemcpyAsync(&host, &at<Counters>(ws, w.counters)->pairs, sizeof(host),
+  Counters* c = at<Counters>(ws, w.counters);
+  hipError_t e = hipMemcpyAsync(&host, adj ? &c->pairs_adj : &c->pairs, sizeof(host),
                                 hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(e, "pair count read-back");
@@ -417,6 +490,14 @@ int g3pcf_workspace_bytes(const g3pcf_problem* prob, int backward, size_t* bytes
   return G3PCF_OK;
 }
 
+int g3pcf_alm_bytes(const g3pcf_problem* prob, size_t* bytes) {
+  int rc = validate(prob);
+  if (rc) return rc;
+  if (!bytes) return fail(G3PCF_EINVAL, "bytes is NULL");
+  *bytes = alm_total(*prob, make_layout(prob->lmax, prob->nbins));
+  return G3PCF_OK;
+}
+
 int g3pcf_forward(const g3pcf_problem* prob, double* zeta, void* ws, size_t ws_bytes,
                   void* stream) {
   int rc = validate(prob);
@@ -425,6 +506,9 @@ int g3pcf_forward(const g3pcf_problem* prob, double* zeta, void* ws, size_t ws_b
   const g3pcf_problem& p = *prob;
   const Ws w = plan(p, 0);
   if ((rc = check_workspace(w, ws, ws_bytes))) return rc;
+  if (p.alm && p.distinct)
+    return fail(G3PCF_EINVAL, "alm store with distinct = 1 (the adjoint does not cover it)");
+  if ((rc = check_alm(p, w))) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
   if ((rc = forward_tables(p))) return rc;
   const size_t zlen = g3pcf_zeta_len(p.lmax, p.nbins);
@@ -432,14 +516,19 @@ int g3pcf_forward(const g3pcf_problem* prob, double* zeta, void* ws, size_t ws_b
   if (!p.accumulate && (e = launch_fill_double(zeta, int64_t(zlen), 0.0, st)) != hipSuccess)
     return hip_fail(e, "zeta clear");
   if (p.n == 0) {
+    if (p.alm && (e = launch_fill_int(static_cast<int*>(p.alm), 2, 0, st)) != hipSuccess)
+      return hip_fail(e, "alm store header");
     if (p.pairs_out) *p.pairs_out = 0;
     return G3PCF_OK;
   }
   {
     StageScope sc(p.trace, G3PCF_STAGE_CELLS, st);
     if ((rc = stage_catalogue(p, w, ws, st))) return rc;
+    if (p.alm && (e = fingerprint(p, w, ws, static_cast<unsigned long long*>(p.alm), st)) !=
+                     hipSuccess)
+      return hip_fail(e, "alm store fingerprint");
   }
-  if ((rc = forward_pairs(p, w, ws, zeta, p.n, st))) return rc;
+  if ((rc = forward_pairs(p, w, ws, zeta, p.n, p.alm ? alm_rows(p) : nullptr, st))) return rc;
   return finish_pairs(p, w, ws, st);
 }
 
@@ -450,6 +539,7 @@ int g3pcf_forward_regions(const g3pcf_problem* prob, const int32_t* region, int 
   if (nregions < 1 || nregions > (1 << 20)) return fail(G3PCF_EINVAL, "nregions must be 1..2^20");
   if (!zeta) return fail(G3PCF_EINVAL, "zeta is NULL");
   if (!region && prob->n > 0) return fail(G3PCF_EINVAL, "region is NULL");
+  if (prob->alm) return fail(G3PCF_EINVAL, "alm store is not kept per region (set it to NULL)");
   const g3pcf_problem& p = *prob;
   const Ws w = plan(p, 0);
   if ((rc = check_workspace(w, ws, ws_bytes))) return rc;
@@ -484,7 +574,7 @@ int g3pcf_forward_regions(const g3pcf_problem* prob, const int32_t* region, int 
             hipSuccess ||
         (e = hipStreamSynchronize(st)) != hipSuccess)
       return hip_fail(e, "region primary count");
-    if (count > 0 && (rc = forward_pairs(p, w, ws, zeta + zlen * size_t(r), count, st)))
+    if (count > 0 && (rc = forward_pairs(p, w, ws, zeta + zlen * size_t(r), count, nullptr, st)))
       return rc;
   }
   return finish_pairs(p, w, ws, st);
@@ -500,10 +590,8 @@ int g3pcf_backward(const g3pcf_problem* prob, const double* grad_zeta, double* g
     return fail(G3PCF_EUNSUPPORTED, "the adjoint does not cover distinct = 1");
   const g3pcf_problem& p = *prob;
   const Ws w = plan(p, 1);
-  if (!ws || ws_bytes < w.total)
-    return fail(G3PCF_EWORKSPACE, "workspace needs " + std::to_string(w.total) + " bytes");
-  if (reinterpret_cast<uintptr_t>(ws) % kAlign)
-    return fail(G3PCF_EWORKSPACE, "workspace must be 256-byte aligned");
+  if ((rc = check_workspace(w, ws, ws_bytes))) return rc;
+  if ((rc = check_alm(p, w))) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
   if ((rc = ensure_tables(p.basis))) return rc;
   if (p.n == 0) {
@@ -511,9 +599,12 @@ int g3pcf_backward(const g3pcf_problem* prob, const double* grad_zeta, double* g
     return G3PCF_OK;
   }
   hipError_t e;
+  Counters* c = at<Counters>(ws, w.counters);
   {
     StageScope sc(p.trace, G3PCF_STAGE_CELLS, st);
     if ((rc = stage_catalogue(p, w, ws, st))) return rc;
+    if (p.alm && (e = fingerprint(p, w, ws, &c->inputs_hash, st)) != hipSuccess)
+      return hip_fail(e, "input fingerprint");
   }
   double* gsort = at<double>(ws, w.gsort);
   if ((e = launch_fill_double(gsort, p.n, 0.0, st)) != hipSuccess)
@@ -529,7 +620,6 @@ int g3pcf_backward(const g3pcf_problem* prob, const double* grad_zeta, double* g
   }
   PairArgs a = pair_args(p, w, ws);
   const int fp64 = (p.pair_prec == G3PCF_PREC_FP64);
-  Counters* c = at<Counters>(ws, w.counters);
   const ConvTable* tab = nullptr;
   if ((e = conv_table_device(p.basis, &tab)) != hipSuccess) return hip_fail(e, "table address");
   a.gcoef = at<double>(ws, w.gcoef);
@@ -539,7 +629,10 @@ int g3pcf_backward(const g3pcf_problem* prob, const double* grad_zeta, double* g
     a.p_begin = b0;
     a.p_count = std::min<int64_t>(w.PB, p.n - b0);
     a.pairs = &c->pairs;
-    {
+    if (p.alm) {
+      // the a_lm rows the forward pass kept
+      a.A = alm_rows(p) + size_t(b0) * w.lay.W;
+    } else {
       StageScope sc(p.trace, G3PCF_STAGE_PAIRS, st);
       if ((e = launch_pair_forward(a, fp64, p.basis, st)) != hipSuccess)
         return hip_fail(e, "pair kernel (recompute)");
@@ -571,10 +664,11 @@ int g3pcf_backward(const g3pcf_problem* prob, const double* grad_zeta, double* g
         return hip_fail(e, "pair adjoint kernel");
     }
   }
-  if ((e = launch_unpermute(gsort, gsort32, a.perm, p.n, p.accumulate, grad_w, st)) !=
-      hipSuccess)
+  const unsigned long long* saved = p.alm ? static_cast<const unsigned long long*>(p.alm) : nullptr;
+  if ((e = launch_unpermute(gsort, gsort32, a.perm, p.n, p.accumulate, saved, &c->inputs_hash, grad_w,
+                            st)) != hipSuccess)
     return hip_fail(e, "gradient permute");
-  return finish_pairs(p, w, ws, st);
+  return finish_pairs(p, w, ws, st, true);
 }
 
 int g3pcf_isotropic(int lmax, int nbins, const double* zeta, double* iso, void* stream) {

@@ -195,7 +195,62 @@ __global__ void k_scan_add(int* __restrict__ out, int64_t count,
 
 inline unsigned blocks_for(int64_t n, int bs) { return unsigned((n + bs - 1) / bs); }
 
+// splitmix64 output function (Steele, Lea and Flood, OOPSLA 2014)
+__device__ __forceinline__ unsigned long long mix64(unsigned long long x) {
+  x ^= x >> 30;
+  x *= 0xbf58476d1ce4e5b9ull;
+  x ^= x >> 27;
+  x *= 0x94d049bb133111ebull;
+  return x ^ (x >> 31);
+}
+
+constexpr int kPrintBlocks = 1024;
+
+// Fingerprint of everything the a_lm rows depend on besides the settings:
+// per cell-order slot its original index, stored position words and weight,
+// and the primary list.  A wrapping sum of per-slot hashes (one atomic per
+// workgroup), so the value does not depend on the order of the atomics.
+__global__ __launch_bounds__(256) void k_fingerprint(const unsigned* __restrict__ pos_words,
+                                                     int words, const double* __restrict__ wsort,
+                                                     const int* __restrict__ perm,
+                                                     const int* __restrict__ plist,
+                                                     const long long* __restrict__ nprim,
+                                                     int64_t n, unsigned long long seed,
+                                                     unsigned long long* __restrict__ out) {
+  __shared__ unsigned long long part[256 / kWave];
+  const long long np = *nprim;
+  unsigned long long h = 0;
+  for (int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < n;
+       s += int64_t(gridDim.x) * blockDim.x) {
+    unsigned long long x = mix64(seed + (unsigned long long)s);
+    x = mix64(x ^ (unsigned)perm[s]);
+    for (int k = 0; k < words; ++k) x = mix64(x ^ pos_words[s * words + k]);
+    x = mix64(x ^ (unsigned long long)__double_as_longlong(wsort[s]));
+    h += x;
+    if (s < np) h += mix64(~seed ^ ((unsigned long long)s << 32) ^ (unsigned)plist[s]);
+  }
+  for (int off = kWave / 2; off > 0; off >>= 1) h += __shfl_xor(h, off);
+  const int wave = threadIdx.x / kWave;
+  if (threadIdx.x % kWave == 0) part[wave] = h;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int k = 0; k < int(blockDim.x) / kWave; ++k) t += part[k];
+    atomicAdd(out, t);
+  }
+}
+
 }  // namespace
+
+hipError_t launch_fingerprint(const void* pos4, int fp64, const double* wsort, const int* perm,
+                              const int* plist, const long long* nprim, int64_t n,
+                              unsigned long long seed, unsigned long long* out, hipStream_t st) {
+  const unsigned nb = std::min<unsigned>(kPrintBlocks, std::max(1u, blocks_for(n, 256)));
+  hipLaunchKernelGGL(k_fingerprint, dim3(nb), dim3(256), 0, st,
+                     static_cast<const unsigned*>(pos4), fp64 ? 8 : 4, wsort, perm, plist, nprim,
+                     n, seed, out);
+  return hipGetLastError();
+}
 
 size_t scan_tmp_bytes(int64_t count) {
   size_t total = 0;

@@ -140,6 +140,12 @@ hipError_t launch_cells(const g3pcf_problem& p, const Grid& g, void* pos4, int* 
 hipError_t launch_primaries(const uint8_t* mask, const int32_t* region, int r, const int* perm,
                             int64_t n, int* flags, int* plist, long long* nprim,
                             void* scan_tmp, size_t scan_tmp_bytes, hipStream_t st);
+// *out += order-independent hash of the cell-order catalogue (slot -> index,
+// stored position words, weight) and the primary list, keyed by `seed` (a hash
+// of the settings); *out must be cleared first.
+hipError_t launch_fingerprint(const void* pos4, int fp64, const double* wsort, const int* perm,
+                              const int* plist, const long long* nprim, int64_t n,
+                              unsigned long long seed, unsigned long long* out, hipStream_t st);
 hipError_t launch_fill_int(int* p, int64_t count, int value, hipStream_t st);
 hipError_t launch_fill_double(double* p, int64_t count, double value, hipStream_t st);
 hipError_t launch_pair_forward(const PairArgs& a, int fp64, int basis, hipStream_t st);
@@ -191,9 +197,11 @@ struct AdjArgs {
 size_t adj_matrix_doubles(const RowLayout& L);
 hipError_t launch_adj_matrix(const double* gz, const RowLayout& L, double* MHt, hipStream_t st);
 hipError_t launch_adj_coef(const AdjArgs& a, hipStream_t st);
-// grad[perm[s]] (=|+=) gs[s] (+ gs32[s] when gs32 is not null)
+// grad[perm[s]] (=|+=) gs[s] (+ gs32[s] when gs32 is not null); NaN instead
+// when fp_saved is not null and *fp_saved != *fp_now
 hipError_t launch_unpermute(const double* gs, const float* gs32, const int* perm, int64_t n,
-                            int accumulate, double* grad, hipStream_t st);
+                            int accumulate, const unsigned long long* fp_saved,
+                            const unsigned long long* fp_now, double* grad, hipStream_t st);
 // Device address of the uploaded conversion table of a basis.
 hipError_t conv_table_device(int basis, const ConvTable** out);
 

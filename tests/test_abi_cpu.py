@@ -206,3 +206,36 @@ def test_regions_reject_bad_arguments_before_device_work(lib, nregions, region):
     rc = lib.g3pcf_forward_regions(ctypes.byref(p), ctypes.c_void_p(region) if region else None,
                                    nregions, ctypes.c_void_p(0x4000), None, 0, None)
     assert rc == _lib.EINVAL
+
+
+def test_alm_store_size(lib):
+    """256-byte header and one row of nbins (lmax+1)^2 doubles per galaxy."""
+    for n, nbins, lmax in [(100, 4, 4), (1 << 20, 10, 10), (0, 1, 0), (7, 32, 10)]:
+        p = _problem(n=n, nbins=nbins, lmax=lmax, rmax=20.0)
+        assert _lib.alm_bytes(p) == 256 + n * nbins * (lmax + 1) ** 2 * 8
+    out = ctypes.c_size_t(0)
+    assert lib.g3pcf_alm_bytes(None, ctypes.byref(out)) == _lib.EINVAL
+    assert lib.g3pcf_alm_bytes(ctypes.byref(_problem()), None) == _lib.EINVAL
+    assert lib.g3pcf_alm_bytes(ctypes.byref(_problem(lmax=11)), ctypes.byref(out)) == _lib.EINVAL
+
+
+def test_alm_store_checked_before_device_work(lib):
+    ws, big = ctypes.c_void_p(0x100000), 1 << 40
+    zeta, gz, gw = ctypes.c_void_p(0x3000), ctypes.c_void_p(0x3000), ctypes.c_void_p(0x4000)
+    p = _problem()
+    need = _lib.alm_bytes(p)
+    # too small, misaligned
+    for addr, nbytes in [(0x200000, need - 1), (0x200008, need)]:
+        p.alm, p.alm_bytes = addr, nbytes
+        assert lib.g3pcf_forward(ctypes.byref(p), zeta, ws, big, None) == _lib.EWORKSPACE
+        assert b"alm" in lib.g3pcf_last_error()
+        assert lib.g3pcf_backward(ctypes.byref(p), gz, gw, ws, big, None) == _lib.EWORKSPACE
+    # a store with distinct = 1 (no adjoint) and with the per-region forward
+    p = _problem(distinct=1)
+    p.alm, p.alm_bytes = 0x200000, need
+    assert lib.g3pcf_forward(ctypes.byref(p), zeta, ws, big, None) == _lib.EINVAL
+    p = _problem()
+    p.alm, p.alm_bytes = 0x200000, need
+    assert lib.g3pcf_forward_regions(ctypes.byref(p), ctypes.c_void_p(0x5000), 4, zeta, ws, big,
+                                     None) == _lib.EINVAL
+    assert b"region" in lib.g3pcf_last_error()
