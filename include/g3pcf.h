@@ -74,8 +74,13 @@ typedef enum { G3PCF_F32 = 0, G3PCF_F64 = 1 } g3pcf_dtype;
 typedef enum {
   G3PCF_BASIS_CARTESIAN = 0, /* the paper's monomials (dx/r)^k (dy/r)^p (dz/r)^q,
                                 k+p+q <= 10: 286 sums per shell (eq. 1)          */
-  G3PCF_BASIS_SPIN = 1       /* (dx/r - i dy/r)^m (dz/r)^n, m+n <= 10: 121 real
+  G3PCF_BASIS_SPIN = 1,      /* (dx/r - i dy/r)^m (dz/r)^n, m+n <= 10: 121 real
                                 sums per shell; the same zeta with fewer FMAs    */
+  G3PCF_BASIS_SPIN_T = 2     /* diagnostic only (g3pcf_conj_ylm_via_monomials),
+                                not a problem setting: (dx/r - i dy/r)^m T_n(dz/r)
+                                with Chebyshev polynomials T_n, the basis in which
+                                the FP32 spin adjoint evaluates its per-pair
+                                polynomial (no cancelling coefficients)          */
 } g3pcf_basis;
 
 /* Stages reported by a trace (see g3pcf_trace_create). */

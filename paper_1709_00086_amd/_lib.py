@@ -15,7 +15,7 @@ OK, EINVAL, EWORKSPACE, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -4
 LOS_Z, LOS_OBSERVER = 0, 1
 PREC_FP64, PREC_FP32, PREC_BF16X3 = 0, 1, 2
 F32, F64 = 0, 1
-BASIS_CARTESIAN, BASIS_SPIN = 0, 1
+BASIS_CARTESIAN, BASIS_SPIN, BASIS_SPIN_T = 0, 1, 2  # SPIN_T: diagnostic table only
 
 EXPORTED = ["g3pcf_zeta_len", "g3pcf_num_terms", "g3pcf_workspace_bytes", "g3pcf_forward",
             "g3pcf_backward", "g3pcf_last_error", "g3pcf_conj_ylm_via_monomials",

@@ -593,7 +593,12 @@ int g3pcf_backward(const g3pcf_problem* prob, const double* grad_zeta, double* g
   if ((rc = check_workspace(w, ws, ws_bytes))) return rc;
   if ((rc = check_alm(p, w))) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if ((rc = ensure_tables(p.basis))) return rc;
+  // the FP32 spin adjoint evaluates its per-pair polynomial with Chebyshev
+  // polynomials of u_z (coefficients from the SPIN_T table)
+  const int adj_table = (p.basis == G3PCF_BASIS_SPIN && p.pair_prec == G3PCF_PREC_FP32)
+                            ? int(G3PCF_BASIS_SPIN_T)
+                            : int(p.basis);
+  if ((rc = ensure_tables(p.basis)) || (rc = ensure_tables(adj_table))) return rc;
   if (p.n == 0) {
     if (p.pairs_out) *p.pairs_out = 0;
     return G3PCF_OK;
@@ -621,7 +626,7 @@ int g3pcf_backward(const g3pcf_problem* prob, const double* grad_zeta, double* g
   PairArgs a = pair_args(p, w, ws);
   const int fp64 = (p.pair_prec == G3PCF_PREC_FP64);
   const ConvTable* tab = nullptr;
-  if ((e = conv_table_device(p.basis, &tab)) != hipSuccess) return hip_fail(e, "table address");
+  if ((e = conv_table_device(adj_table, &tab)) != hipSuccess) return hip_fail(e, "table address");
   a.gcoef = at<double>(ws, w.gcoef);
   a.grad_w = gsort;
   a.grad_w32 = gsort32;

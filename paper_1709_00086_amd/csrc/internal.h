@@ -16,9 +16,13 @@ namespace g3 {
 constexpr int kDeg = 10;
 constexpr int kTermsCart = (kDeg + 1) * (kDeg + 2) * (kDeg + 3) / 6;  // 286
 constexpr int kTermsSpin = (kDeg + 1) * (kDeg + 1);                   // 121 real sums
+// Conversion tables: G3PCF_BASIS_CARTESIAN, G3PCF_BASIS_SPIN and
+// G3PCF_BASIS_SPIN_T (the spin terms with T_n(u_z) in place of u_z^n; only the
+// FP32 spin adjoint uses it).
+constexpr int kConvTables = 3;
 // Internal "basis" of the pass that collects the degenerate (j = k) triangles:
 // per shell the sums w_j^2 P_n(u_z) of Legendre polynomials, n <= 2 kDeg.
-constexpr int kBasisDeg = 2;
+constexpr int kBasisDeg = 3;
 constexpr int kTermsDeg = 2 * kDeg + 1;                               // 21
 constexpr int kMaxBins = 32;
 constexpr int kWave = 64;

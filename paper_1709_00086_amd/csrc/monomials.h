@@ -440,6 +440,56 @@ struct SpinChunk {
   }
 };
 
+// Adjoint polynomial of the FP32 spin path: the sum over (m, n) of the
+// coefficients times the Re / Im parts of (x - i y)^m T_n(z), with Chebyshev
+// polynomials T_n in place of z^n.  In this basis the coefficients of the
+// spherical harmonics do not cancel (those of z^n do, by two to three orders
+// of magnitude at l = 10), so FP32 evaluation keeps close to FP32 accuracy.
+// The coefficients are the same for every lane (one set per primary and
+// shell) and are held in vector registers: an FMA with a scalar-register
+// operand issues more slowly than one with three vector registers.
+struct SpinTPoly {
+  float g[kTermsSpin];
+
+  template <typename Ptr>
+  __device__ __forceinline__ void load(Ptr gc) {
+#pragma unroll
+    for (int t = 0; t < kTermsSpin; ++t) g[t] = float(gc[t]);
+  }
+
+  __device__ __forceinline__ float eval(float x, float y, float z) const {
+    float tn[kDeg + 1];
+    tn[0] = 1.0f;
+    tn[1] = z;
+    const float z2 = z + z;
+#pragma unroll
+    for (int n = 1; n < kDeg; ++n) tn[n + 1] = fma_r(z2, tn[n], -tn[n - 1]);
+    float total = g[spin_index_c(0, 0, 0)];
+    static_for<kDeg>([&](auto nc) {
+      constexpr int n = decltype(nc)::value + 1;
+      total = fma_r(g[spin_index_c(0, n, 0)], tn[n], total);
+    });
+    float cr = x, ci = -y;  // (x - i y)^m, m = 1
+    static_for<kDeg>([&](auto mc) {
+      constexpr int m = decltype(mc)::value + 1;
+      if constexpr (m > 1) {
+        const float nr = fma_r(cr, x, ci * y);
+        const float ni = fma_r(ci, x, -(cr * y));
+        cr = nr;
+        ci = ni;
+      }
+      float hr = g[spin_index_c(m, 0, 0)], hi = g[spin_index_c(m, 0, 1)];
+      static_for<kDeg - m>([&](auto nc) {
+        constexpr int n = decltype(nc)::value + 1;
+        hr = fma_r(g[spin_index_c(m, n, 0)], tn[n], hr);
+        hi = fma_r(g[spin_index_c(m, n, 1)], tn[n], hi);
+      });
+      total = fma_r(cr, hr, fma_r(ci, hi, total));
+    });
+    return total;
+  }
+};
+
 template <class... C>
 struct ChunkList {};
 

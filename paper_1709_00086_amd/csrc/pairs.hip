@@ -47,11 +47,11 @@
 
 namespace g3 {
 
-__device__ ConvTable g_conv[2];
+__device__ ConvTable g_conv[kConvTables];
 
 hipError_t upload_tables(int basis) {
-  static ConvTable host[2];
-  static bool built[2] = {false, false};
+  static ConvTable host[kConvTables];
+  static bool built[kConvTables] = {};
   if (!built[basis]) {
     build_conv_table(basis, &host[basis]);
     built[basis] = true;
@@ -97,7 +97,9 @@ struct WaveLds {
   RunEntry<Real> run[kMaxRuns];
   V ring[kRing];               // (d_x, d_y, d_z, w) forward; (d_x, d_y, d_z, index) adjoint
   int ring_j[kRing];           // secondary index of a ring entry (when spilled)
-  Real M[ADJ ? 1 : kTermsCart + 1];  // (+1 padding slot)
+  // forward: the reduced sums (+1 padding slot); FP32 adjoint: the shell's
+  // polynomial coefficients on their way into vector registers
+  Real M[ADJ ? (std::is_same<Real, float>::value ? kTermsSpin + 3 : 1) : kTermsCart + 1];
 };
 
 __device__ __forceinline__ void wave_lds_fence() {
@@ -233,13 +235,19 @@ struct Bin64 {
 };
 
 // Occupancy target per kernel (waves per SIMD); the register budget is
-// 512 / target per lane, so every accumulator chunk must fit.  The adjoint
-// holds no accumulators: at four waves it spills a few values outside its
-// loops and hides more of its atomics' latency (5-11% faster than three).
+// 512 / target per lane, so every accumulator chunk must fit.  The FP64 and
+// cartesian adjoints hold no accumulators: at four waves they spill a few
+// values outside their loops and hide more of their atomics' latency (5-11%
+// faster than three).  The FP32 spin adjoint holds its 121 coefficients in
+// vector registers, like the forward's 121 sums: three waves.
 template <typename Real, int BASIS, bool ADJOINT>
 struct Occ {
-  static constexpr int value =
-      (ADJOINT || BASIS == kBasisDeg) ? 4 : (std::is_same<Real, float>::value ? 3 : 2);
+  static constexpr bool kSpinT =
+      ADJOINT && std::is_same<Real, float>::value && BASIS == G3PCF_BASIS_SPIN;
+  static constexpr int value = kSpinT ? 3
+                               : (ADJOINT || BASIS == kBasisDeg)
+                                   ? 4
+                                   : (std::is_same<Real, float>::value ? 3 : 2);
 };
 
 template <class... C>
@@ -253,6 +261,8 @@ struct PairKernel {
   using V = typename V4<Real>::T;
   using Lds = WaveLds<Real, ADJOINT>;
   static constexpr bool kF32 = std::is_same<Real, float>::value;
+  // FP32 spin adjoint: Chebyshev-basis polynomial in FP32 (SpinTPoly)
+  static constexpr bool kSpinT = Occ<Real, BASIS, ADJOINT>::kSpinT;
   static constexpr int kTerms = (BASIS == G3PCF_BASIS_SPIN) ? kTermsSpin
                                 : (BASIS == kBasisDeg)      ? kTermsDeg
                                                             : kTermsCart;
@@ -742,13 +752,35 @@ struct PairKernel {
     } else {
       // the shell's coefficients, read through the scalar cache (uniform)
       const CoefPtr gc = (CoefPtr)(a.gcoef + (row * a.nbins + b) * kTerms);
-      got = search_shell<MINIMG, false>(a, W, pos4, P, b, r0, r1,
-                                        [&](const V& e, int, bool valid) {
-                                          Real ux, uy, uz;
-                                          unit<ROT>(P, e, ux, uy, uz);
-                                          scatter_one(a, gc, ux, uy, uz, unpack_index(e.w), valid,
-                                                      w_prim);
-                                        });
+      if constexpr (kSpinT) {
+        // FP32 spin: Chebyshev-basis coefficients, converted once per shell
+        // and staged through LDS (one vector load per lane, then broadcast
+        // reads) into vector registers; FP32 polynomial and FP32 atomics
+        const double* gv = a.gcoef + (row * a.nbins + b) * kTerms;
+        for (int t = lane; t < kTermsSpin; t += kWave) W.M[t] = float(gv[t]);
+        wave_lds_fence();
+        SpinTPoly poly;
+        poly.load(W.M);
+        wave_lds_fence();
+        const float wp = float(w_prim);
+        got = search_shell<MINIMG, false>(a, W, pos4, P, b, r0, r1,
+                                          [&](const V& e, int, bool valid) {
+                                            Real ux, uy, uz;
+                                            unit<ROT>(P, e, ux, uy, uz);
+                                            const float v = poly.eval(ux, uy, uz);
+                                            if (valid)
+                                              unsafeAtomicAdd(&a.grad_w32[unpack_index(e.w)],
+                                                              wp * v);
+                                          });
+      } else {
+        got = search_shell<MINIMG, false>(a, W, pos4, P, b, r0, r1,
+                                          [&](const V& e, int, bool valid) {
+                                            Real ux, uy, uz;
+                                            unit<ROT>(P, e, ux, uy, uz);
+                                            scatter_one(a, gc, ux, uy, uz, unpack_index(e.w),
+                                                        valid, w_prim);
+                                          });
+      }
       wave_lds_fence();
     }
     return got;

@@ -98,6 +98,22 @@ void build_conv_table(int basis, ConvTable* t) {
             t->coef[nnz] = scale * double(c_int(l, m, k));
             ++nnz;
           }
+        } else if (basis == G3PCF_BASIS_SPIN_T) {
+          // u_z^n = 2^(1-n) sum_j binom(n, j) T_{n-2j}(u_z), the T_0 term halved
+          std::map<int, double> acc;
+          for (int k = 0; 2 * k <= l - m; ++k) {
+            const int n = l - m - 2 * k;
+            const double c = scale * double(c_int(l, m, k));
+            for (int j = 0; 2 * j <= n; ++j) {
+              const double a = std::ldexp(double(binom(n, j)), (2 * j == n) ? -n : 1 - n);
+              acc[n - 2 * j] += c * a;
+            }
+          }
+          for (auto& kv : acc) {
+            t->term[nnz] = short(spin_index(m, kv.first, part));
+            t->coef[nnz] = kv.second;
+            ++nnz;
+          }
         } else {
           // exact integer coefficients of u_x^K u_y^P u_z^Q for this (l, m, part)
           std::map<std::tuple<int, int, int>, int64_t> acc;
@@ -136,7 +152,7 @@ void build_conv_table(int basis, ConvTable* t) {
   t->nout = o;
   t->nnz = nnz;
   // transpose: entries grouped by term
-  const int nterm = (basis == G3PCF_BASIS_SPIN) ? kTermsSpin : kTermsCart;
+  const int nterm = (basis == G3PCF_BASIS_CARTESIAN) ? kTermsCart : kTermsSpin;
   std::vector<int> cnt(nterm + 1, 0);
   for (int e = 0; e < nnz; ++e) cnt[t->term[e] + 1]++;
   for (int k = 0; k < nterm; ++k) cnt[k + 1] += cnt[k];
@@ -235,29 +251,34 @@ void build_deg_table(double* G) {
 extern "C" int g3pcf_conj_ylm_via_monomials(int basis, int lmax, double ux, double uy,
                                             double uz, double* out) {
   using namespace g3;
-  if ((basis != G3PCF_BASIS_CARTESIAN && basis != G3PCF_BASIS_SPIN) || lmax < 0 ||
-      lmax > kDeg || out == nullptr)
+  if ((basis != G3PCF_BASIS_CARTESIAN && basis != G3PCF_BASIS_SPIN &&
+       basis != G3PCF_BASIS_SPIN_T) ||
+      lmax < 0 || lmax > kDeg || out == nullptr)
     return G3PCF_EINVAL;
-  static thread_local ConvTable tab[2];
-  static thread_local bool built[2] = {false, false};
+  static thread_local ConvTable tab[kConvTables];
+  static thread_local bool built[kConvTables] = {};
   if (!built[basis]) {
     build_conv_table(basis, &tab[basis]);
     built[basis] = true;
   }
   const ConvTable& t = tab[basis];
-  std::vector<double> M(basis == G3PCF_BASIS_SPIN ? kTermsSpin : kTermsCart, 0.0);
-  if (basis == G3PCF_BASIS_SPIN) {
+  std::vector<double> M(basis == G3PCF_BASIS_CARTESIAN ? kTermsCart : kTermsSpin, 0.0);
+  if (basis != G3PCF_BASIS_CARTESIAN) {
+    // u_z^n, or T_n(u_z) from T_{n+1} = 2 u_z T_n - T_{n-1}
+    double zn[kDeg + 1];
+    zn[0] = 1.0;
+    zn[1] = uz;
+    for (int n = 1; n < kDeg; ++n)
+      zn[n + 1] = (basis == G3PCF_BASIS_SPIN_T) ? 2.0 * uz * zn[n] - zn[n - 1] : zn[n] * uz;
     double cr = 1.0, ci = 0.0;  // (ux - i uy)^m
     for (int m = 0; m <= kDeg; ++m) {
-      double zn = 1.0;
       for (int n = 0; m + n <= kDeg; ++n) {
         if (m == 0) {
-          M[spin_index(0, n, 0)] = zn;
+          M[spin_index(0, n, 0)] = zn[n];
         } else {
-          M[spin_index(m, n, 0)] = cr * zn;
-          M[spin_index(m, n, 1)] = ci * zn;
+          M[spin_index(m, n, 0)] = cr * zn[n];
+          M[spin_index(m, n, 1)] = ci * zn[n];
         }
-        zn *= uz;
       }
       const double nr = cr * ux + ci * uy, ni = ci * ux - cr * uy;
       cr = nr;

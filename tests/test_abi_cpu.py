@@ -60,8 +60,10 @@ def test_sizes_match_the_paper(lib):
     assert 128 * 8 * 3 + T * 8 * 8 == gold["working_set_bytes"]["value"]
 
 
-@pytest.mark.parametrize("basis", [_lib.BASIS_CARTESIAN, _lib.BASIS_SPIN])
+@pytest.mark.parametrize("basis", [_lib.BASIS_CARTESIAN, _lib.BASIS_SPIN, _lib.BASIS_SPIN_T])
 def test_conversion_table_reproduces_scipy_ylm(lib, basis):
+    """conj(Y_lm) through each table: the paper's monomials, the spin sums, and
+    the spin sums with T_n(u_z) (the FP32 adjoint's basis)."""
     from scipy.special import sph_harm_y
     rng = np.random.default_rng(3)
     U = rng.standard_normal((300, 3))
@@ -119,6 +121,7 @@ def _problem(**kw):
     dict(pair_prec=_lib.PREC_BF16X3),
     dict(zeta_prec=9),
     dict(basis=3),
+    dict(basis=_lib.BASIS_SPIN_T),    # a diagnostic table, not a problem setting
     dict(accumulate=2),
     dict(distinct=2),
 ])
