@@ -84,9 +84,9 @@ def main():
     ap.add_argument("--regions", type=int, default=0, metavar="K",
                     help="partial zeta of K^3 spatial cubes of primaries (jack-knife regions; "
                          "forward only)")
-    ap.add_argument("--recompute", action="store_true",
-                    help="backward recomputes the a_lm on the pair kernel instead of reading "
-                         "the a_lm store the forward filled")
+    ap.add_argument("--keep-alm", action="store_true",
+                    help="the forward keeps the a_lm in a store (n * nbins * (lmax+1)^2 "
+                         "doubles) and the backward reads them instead of recomputing them")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--sample", type=int, default=8192,
@@ -144,10 +144,11 @@ def main():
         zeta_regions_out = torch.empty((k ** 3,) + api.zeta_shape(cat.lmax, cat.nbins),
                                        dtype=torch.float64, device=dev)
 
-    # the a_lm store (one row per primary, kept from the forward for the
-    # backward; allocated once like the workspace, rewritten by every forward)
+    # the backward recomputes the a_lm on the pair kernel; --keep-alm keeps
+    # them in a store instead (one row per primary, allocated once like the
+    # workspace, rewritten by every forward)
     store = None
-    if not args.forward_only and not args.recompute:
+    if not args.forward_only and args.keep_alm:
         store = api.alm_store(pos, w, cfg)
         log(f"a_lm store: {store.numel() / 1e9:.2f} GB")
 

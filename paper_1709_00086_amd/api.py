@@ -234,7 +234,8 @@ def isotropic(zeta_t: torch.Tensor, lmax: int, nbins: int) -> torch.Tensor:
 
 def _keep_alm(pos: torch.Tensor, w: torch.Tensor, cfg: Config, keep) -> Optional[torch.Tensor]:
     """The a_lm store for an autograd forward: always (keep=True), never
-    (False), or (None) when it takes at most a quarter of the free device memory."""
+    (False, the default: the backward recomputes the a_lm), or (None) when it
+    takes at most a quarter of the free device memory."""
     if keep is False or cfg.distinct:
         return None
     nbytes = _lib.alm_bytes(make_problem(pos, w, cfg))
@@ -248,14 +249,16 @@ def _keep_alm(pos: torch.Tensor, w: torch.Tensor, cfg: Config, keep) -> Optional
 class G3PCF(torch.autograd.Function):
     """zeta as a differentiable function of the weights.
 
-    forward(w, pos, cfg, primary_mask, keep_alm) -> zeta.  Saves ``pos``, ``w``,
-    the mask and, unless keep_alm is False (or it would not fit, keep_alm None),
-    the a_lm store, so that the backward pass does not recompute the a_lm on the
-    pair kernel.  Position gradients are not provided (None).
+    forward(w, pos, cfg, primary_mask, keep_alm) -> zeta.  Saves ``pos``, ``w``
+    and the mask; the backward pass recomputes the a_lm on the pair kernel
+    (about n * nbins * (lmax+1)^2 * 8 bytes are never held).  keep_alm=True
+    (or None: when it fits in a quarter of the free device memory) also keeps
+    the a_lm store, and the backward reads the a_lm from it instead.
+    Position gradients are not provided (None).
     """
 
     @staticmethod
-    def forward(ctx, w, pos, cfg: Config, primary_mask=None, keep_alm=None):
+    def forward(ctx, w, pos, cfg: Config, primary_mask=None, keep_alm=False):
         ctx.cfg = cfg
         ctx.save_for_backward(w, pos, primary_mask if primary_mask is not None else
                               torch.empty(0, dtype=torch.uint8, device=pos.device))
@@ -273,6 +276,6 @@ class G3PCF(torch.autograd.Function):
         return gw, None, None, None, None
 
 
-def zeta_autograd(w, pos, cfg: Config, primary_mask=None, keep_alm=None):
+def zeta_autograd(w, pos, cfg: Config, primary_mask=None, keep_alm=False):
     """zeta through torch.autograd; keep_alm as in :class:`G3PCF`."""
     return G3PCF.apply(w, pos, cfg, primary_mask, keep_alm)

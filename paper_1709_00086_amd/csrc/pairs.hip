@@ -90,16 +90,20 @@ struct RunEntry<double> {
 
 // ---------------------------------------------------------------- per-wave LDS
 // M holds the shell's reduced monomial sums (forward only).
-template <typename Real, bool ADJ>
+// FP32 spin adjoint: (secondary, term) pairs waiting for their atomic add.
+constexpr int kOutBuf = 8 * kWave;
+
+template <typename Real, bool ADJ, bool SPINT = false>
 struct WaveLds {
   using V = typename V4<Real>::T;
   int pre[kMaxRuns];           // first virtual candidate index of each run
   RunEntry<Real> run[kMaxRuns];
   V ring[kRing];               // (d_x, d_y, d_z, w) forward; (d_x, d_y, d_z, index) adjoint
   int ring_j[kRing];           // secondary index of a ring entry (when spilled)
-  // forward: the reduced sums (+1 padding slot); FP32 adjoint: the shell's
-  // polynomial coefficients on their way into vector registers
-  Real M[ADJ ? (std::is_same<Real, float>::value ? kTermsSpin + 3 : 1) : kTermsCart + 1];
+  // forward: the reduced sums (+1 padding slot); FP32 spin adjoint: the
+  // shell's polynomial coefficients on their way into vector registers
+  Real M[ADJ ? (SPINT ? kTermsSpin + 3 : 1) : kTermsCart + 1];
+  int2 out[SPINT ? kOutBuf : 1];
 };
 
 __device__ __forceinline__ void wave_lds_fence() {
@@ -259,10 +263,10 @@ constexpr int n_chunks(ChunkList<C...>) {
 template <typename Real, int BASIS, bool ADJOINT>
 struct PairKernel {
   using V = typename V4<Real>::T;
-  using Lds = WaveLds<Real, ADJOINT>;
-  static constexpr bool kF32 = std::is_same<Real, float>::value;
   // FP32 spin adjoint: Chebyshev-basis polynomial in FP32 (SpinTPoly)
   static constexpr bool kSpinT = Occ<Real, BASIS, ADJOINT>::kSpinT;
+  using Lds = WaveLds<Real, ADJOINT, kSpinT>;
+  static constexpr bool kF32 = std::is_same<Real, float>::value;
   static constexpr int kTerms = (BASIS == G3PCF_BASIS_SPIN) ? kTermsSpin
                                 : (BASIS == kBasisDeg)      ? kTermsDeg
                                                             : kTermsCart;
@@ -763,15 +767,25 @@ struct PairKernel {
         poly.load(W.M);
         wave_lds_fence();
         const float wp = float(w_prim);
-        got = search_shell<MINIMG, false>(a, W, pos4, P, b, r0, r1,
-                                          [&](const V& e, int, bool valid) {
-                                            Real ux, uy, uz;
-                                            unit<ROT>(P, e, ux, uy, uz);
-                                            const float v = poly.eval(ux, uy, uz);
-                                            if (valid)
-                                              unsafeAtomicAdd(&a.grad_w32[unpack_index(e.w)],
-                                                              wp * v);
-                                          });
+        // Each wave of terms goes to the LDS buffer and the buffer to the
+        // atomics every kOutBuf / kWave waves: a wait for the candidate loads
+        // then finds atomics outstanding (and has to wait for them, vmcnt
+        // counting both) once per flush instead of after every wave of pairs.
+        int nout = 0;
+        got = search_shell<MINIMG, false>(
+            a, W, pos4, P, b, r0, r1, [&](const V& e, int, bool valid) {
+              Real ux, uy, uz;
+              unit<ROT>(P, e, ux, uy, uz);
+              const float v = poly.eval(ux, uy, uz);
+              W.out[nout + lane_here()] =
+                  make_int2(valid ? unpack_index(e.w) : -1, __float_as_int(wp * v));
+              nout += kWave;
+              if (nout == kOutBuf) {
+                flush_terms(a, W, nout);
+                nout = 0;
+              }
+            });
+        if (nout > 0) flush_terms(a, W, nout);
       } else {
         got = search_shell<MINIMG, false>(a, W, pos4, P, b, r0, r1,
                                           [&](const V& e, int, bool valid) {
@@ -972,6 +986,17 @@ struct PairKernel {
     const int lane = threadIdx.x % kWave;
     const int nd = 2 * a.lmax + 1;
     if (lane < nd) a.A[row * a.lay.W + b * nd + lane] = double(W.M[lane]);
+  }
+
+  // The buffered secondary terms of the FP32 spin adjoint into the FP32
+  // gradient (n: a multiple of the wave size; index -1 marks an empty lane).
+  static __device__ __forceinline__ void flush_terms(const PairArgs& a, Lds& W, int n) {
+    wave_lds_fence();
+    for (int k = 0; k < n; k += kWave) {
+      const int2 o = W.out[k + lane_here()];
+      if (o.x >= 0) unsafeAtomicAdd(&a.grad_w32[o.x], __int_as_float(o.y));
+    }
+    wave_lds_fence();
   }
 
   // Adjoint for one pair per lane: the full polynomial sum_t g_t mono_t(u) in

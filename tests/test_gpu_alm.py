@@ -83,7 +83,8 @@ def test_store_matches_recompute_and_oracle(dev, key, basis, precision):
 
 
 def test_autograd_keeps_the_store(dev):
-    """zeta_autograd with keep_alm True / False / None: the same gradient."""
+    """zeta_autograd with keep_alm False (the default: recompute) / True /
+    None (keep when it fits): the same gradient."""
     say("case alm autograd")
     cat = C.config1_weighted()
     pos, w0, _ = tensors(cat, dev)
