@@ -89,6 +89,9 @@ def main():
     ap.add_argument("--regions", type=int, default=0, metavar="K",
                     help="partial zeta of K^3 spatial cubes of primaries (jack-knife regions; "
                          "forward only)")
+    ap.add_argument("--batch", type=int, default=0, metavar="K",
+                    help="K mock catalogues of n/K galaxies each in the workload's box, in one "
+                         "batched forward call (forward only; no CPU baseline or FP64 compare)")
     ap.add_argument("--keep-alm", action="store_true",
                     help="the forward keeps the a_lm in a store (n * nbins * (lmax+1)^2 "
                          "doubles) and the backward reads them instead of recomputing them")
@@ -100,8 +103,11 @@ def main():
                     help="first run one plain device copy of MIB MiB (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
-    if args.distinct or args.regions:
+    if args.distinct or args.regions or args.batch:
         args.forward_only = True
+    if args.batch:
+        args.no_cpu_baseline = True
+        args.no_fp64_compare = True
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus > 1 or world > 1:
@@ -134,8 +140,20 @@ def main():
     ws = api.Workspace()
     zeta_out = torch.empty(api.zeta_shape(cat.lmax, cat.nbins), dtype=torch.float64, device=dev)
 
-    # accepted pairs (counted by the kernel; outside the timed region)
-    _, pairs = api.zeta(pos, w, cfg, out=zeta_out, workspace=ws, return_pairs=True)
+    offs = None
+    if args.batch:
+        # K seeded mock catalogues of the workload's box and dtype in place of it
+        k = args.batch
+        mp, mw, offs = C.mock_batch([cat.n // k] * k, cat.box[0], seed=97, dtype=cat.pos.dtype)
+        pos = torch.from_numpy(mp).to(dev)
+        w = torch.from_numpy(mw).to(dev)
+        zeta_batch_out = torch.empty((k,) + api.zeta_shape(cat.lmax, cat.nbins),
+                                     dtype=torch.float64, device=dev)
+        _, pairs = api.zeta_batch(pos, w, cfg, offs, out=zeta_batch_out, workspace=ws,
+                                  return_pairs=True)
+    else:
+        # accepted pairs (counted by the kernel; outside the timed region)
+        _, pairs = api.zeta(pos, w, cfg, out=zeta_out, workspace=ws, return_pairs=True)
     log(f"accepted ordered pairs: {pairs} ({pairs / cat.n:.1f} per primary)")
 
     region = None
@@ -158,7 +176,9 @@ def main():
         log(f"a_lm store: {store.numel() / 1e9:.2f} GB")
 
     def step(trace=None):
-        if region is not None:
+        if offs is not None:
+            api.zeta_batch(pos, w, cfg, offs, out=zeta_batch_out, workspace=ws, trace=trace)
+        elif region is not None:
             api.zeta_regions(pos, w, cfg, region, args.regions ** 3, out=zeta_regions_out,
                              workspace=ws, trace=trace)
         else:
@@ -195,7 +215,9 @@ def main():
     achieved_tflops = pairs_per_launch * fpp / (avg_launch_ms * 1e-3) / 1e12
     peak = PEAK["fp64_vector_tflops"] if args.precision == "fp64" else PEAK["fp32_vector_tflops"]
     pair_kernel_pairs_per_s = pairs_per_launch / (avg_launch_ms * 1e-3)
-    prof = measured_profile(args.basis, args.precision, args.workload)
+    # the profile covers full pair-blocks of the workload itself
+    prof = measured_profile(args.basis, args.precision,
+                            None if (args.batch or args.regions) else args.workload)
     value = pairs / (ms_per_step * 1e-3)
     log(f"step {ms_per_step:.1f} ms; stages (ms/step) {json.dumps(stage_ms)}")
     log(f"pair kernel: {len(pair_launches)} launches, avg {avg_launch_ms:.2f} ms, "
@@ -230,6 +252,8 @@ def main():
                                                             else "kept from the forward"),
             "distinct": bool(args.distinct),
             "regions": args.regions ** 3 if args.regions else 0,
+            "batch": (f"{args.batch} mock catalogues of {cat.n // args.batch} galaxies "
+                      f"(uniform, seed 97) in the workload's box") if args.batch else None,
             "accepted_pairs": pairs,
         },
         "stage_ms_per_step": stage_ms,

@@ -219,6 +219,22 @@ int g3pcf_forward(const g3pcf_problem* prob, double* zeta, void* ws, size_t ws_b
 int g3pcf_forward_regions(const g3pcf_problem* prob, const int32_t* region, int nregions,
                           double* zeta, void* ws, size_t ws_bytes, void* stream);
 
+/* Forward pass over a batch of ncat catalogues of one geometry (randoms or
+ * mocks sharing the box, shells, lmax, line of sight and precision), the
+ * paper's downstream use (Sec. 6): catalogue c is the galaxies
+ * [offsets[c], offsets[c+1]) of prob's arrays (positions, weights and, if set,
+ * primary_mask), and its zeta goes to zeta + c * g3pcf_zeta_len, computed as
+ * g3pcf_forward would for that catalogue alone (pairs never cross
+ * catalogues).  offsets: HOST [ncat+1], offsets[0] = 0, non-decreasing,
+ * offsets[ncat] = n.  zeta: device [ncat][g3pcf_zeta_len] doubles.  ws: at
+ * least g3pcf_workspace_bytes(prob, 0) bytes for the whole batch; the
+ * catalogues run one after another in it on `stream`.  pairs_out (if set): the
+ * pairs of all catalogues (one wait per catalogue).  alm must be NULL.
+ * Errors as g3pcf_forward, and G3PCF_EINVAL for ncat outside 1..2^20 or
+ * inconsistent offsets. */
+int g3pcf_forward_batch(const g3pcf_problem* prob, int ncat, const int64_t* offsets,
+                        double* zeta, void* ws, size_t ws_bytes, void* stream);
+
 /* Adjoint pass.  With L = sum over the real view of grad_zeta * zeta
  * (grad_zeta laid out like zeta), stores dL/dw_k for every galaxy k in
  * grad_w [n] (added to it when accumulate = 1).  zeta is linear in the weight

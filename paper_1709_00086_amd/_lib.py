@@ -21,7 +21,7 @@ EXPORTED = ["g3pcf_zeta_len", "g3pcf_num_terms", "g3pcf_workspace_bytes", "g3pcf
             "g3pcf_backward", "g3pcf_last_error", "g3pcf_conj_ylm_via_monomials",
             "g3pcf_trace_create", "g3pcf_trace_reset", "g3pcf_trace_read",
             "g3pcf_trace_destroy", "g3pcf_isotropic", "g3pcf_degenerate_term",
-            "g3pcf_forward_regions", "g3pcf_alm_bytes"]
+            "g3pcf_forward_regions", "g3pcf_alm_bytes", "g3pcf_forward_batch"]
 STAGES = {0: "cells", 1: "pairs", 2: "zeta", 3: "adj_coef", 4: "pair_adjoint", 5: "distinct"}
 
 
@@ -80,6 +80,10 @@ def load():
     lib.g3pcf_workspace_bytes.restype = ctypes.c_int
     lib.g3pcf_alm_bytes.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
     lib.g3pcf_alm_bytes.restype = ctypes.c_int
+    lib.g3pcf_forward_batch.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                        ctypes.c_void_p]
+    lib.g3pcf_forward_batch.restype = ctypes.c_int
     lib.g3pcf_forward.argtypes = [P, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                   ctypes.c_void_p]
     lib.g3pcf_forward.restype = ctypes.c_int

@@ -193,6 +193,37 @@ def zeta_regions(pos: torch.Tensor, w: torch.Tensor, cfg: Config, region: torch.
     return out
 
 
+def zeta_batch(pos: torch.Tensor, w: torch.Tensor, cfg: Config, offsets: Sequence[int],
+               primary_mask: Optional[torch.Tensor] = None, accumulate: bool = False,
+               out: Optional[torch.Tensor] = None, workspace: Optional[Workspace] = None,
+               return_pairs: bool = False, trace: Optional["_lib.Trace"] = None):
+    """zeta of each catalogue of a batch, float64 [ncat][m][l][l'][b1][b2][2].
+
+    Catalogue c is rows offsets[c]:offsets[c+1] of ``pos`` / ``w`` (concatenated
+    catalogues of one geometry, e.g. randoms or mocks); pairs never cross
+    catalogues."""
+    import ctypes
+    offs = [int(o) for o in offsets]
+    ncat = len(offs) - 1
+    pairs = ctypes.c_int64(0)
+    p = make_problem(pos, w, cfg, primary_mask, accumulate,
+                     ctypes.pointer(pairs) if return_pairs else None, trace)
+    shape = (ncat,) + zeta_shape(cfg.lmax, cfg.nbins)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float64, device=pos.device)
+    elif out.shape != shape or out.dtype != torch.float64 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float64 tensor of shape " + str(shape))
+    ws = (workspace or _default_ws).get(_lib.workspace_bytes(p, 0), pos.device)
+    stream = torch.cuda.current_stream(pos.device).cuda_stream
+    arr = (ctypes.c_int64 * len(offs))(*offs)
+    _lib.check(_lib.load().g3pcf_forward_batch(
+        ctypes.byref(p), int(ncat), arr, ctypes.c_void_p(out.data_ptr()),
+        ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()), ctypes.c_void_p(stream)))
+    if return_pairs:
+        return out, int(pairs.value)
+    return out
+
+
 def zeta_backward(pos: torch.Tensor, w: torch.Tensor, cfg: Config, grad_zeta: torch.Tensor,
                   primary_mask: Optional[torch.Tensor] = None,
                   workspace: Optional[Workspace] = None,

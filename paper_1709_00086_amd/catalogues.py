@@ -165,6 +165,22 @@ def primary_mask(n: int, count: int, seed: int = 7) -> np.ndarray:
     return m
 
 
+def mock_batch(sizes, L: float, seed: int, dtype=np.float64):
+    """Seeded uniform catalogues of one periodic box L^3 (stand-ins for randoms
+    or mocks of one geometry), concatenated: positions (sum(sizes), 3) of
+    ``dtype``, weights ~ U(0.5, 1.5) float64, and offsets [len(sizes) + 1]
+    int64 (catalogue c is rows offsets[c]:offsets[c+1]).  Draw order per
+    catalogue: positions, then weights."""
+    rng = np.random.default_rng(seed)
+    pos, w = [], []
+    for n in sizes:
+        pos.append(_cast_positions(rng.uniform(0.0, L, size=(n, 3)), dtype, (0.0, 0.0, 0.0),
+                                   (L, L, L)))
+        w.append(rng.uniform(0.5, 1.5, size=n))
+    offs = np.concatenate([[0], np.cumsum(sizes, dtype=np.int64)]).astype(np.int64)
+    return np.concatenate(pos), np.concatenate(w), offs
+
+
 def loss_weights(lmax: int, nbins: int, seed: int = 55) -> np.ndarray:
     """c ~ N(0, 1) float64 shaped like zeta: [m][l][l'][b1][b2][re,im]."""
     rng = np.random.default_rng(seed)

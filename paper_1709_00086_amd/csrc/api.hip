@@ -580,6 +580,53 @@ int g3pcf_forward_regions(const g3pcf_problem* prob, const int32_t* region, int 
   return finish_pairs(p, w, ws, st);
 }
 
+int g3pcf_forward_batch(const g3pcf_problem* prob, int ncat, const int64_t* offsets,
+                        double* zeta, void* ws, size_t ws_bytes, void* stream) {
+  int rc = validate(prob);
+  if (rc) return rc;
+  if (ncat < 1 || ncat > (1 << 20)) return fail(G3PCF_EINVAL, "ncat must be 1..2^20");
+  if (!offsets || !zeta) return fail(G3PCF_EINVAL, "offsets and zeta must be non-NULL");
+  if (offsets[0] != 0 || offsets[ncat] != prob->n)
+    return fail(G3PCF_EINVAL, "offsets must start at 0 and end at n");
+  for (int c = 0; c < ncat; ++c)
+    if (offsets[c + 1] < offsets[c]) return fail(G3PCF_EINVAL, "offsets must not decrease");
+  if (prob->alm) return fail(G3PCF_EINVAL, "alm store is not kept per catalogue (set it to NULL)");
+  const g3pcf_problem& p = *prob;
+  if ((rc = check_workspace(plan(p, 0), ws, ws_bytes))) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((rc = forward_tables(p))) return rc;
+  const size_t zlen = g3pcf_zeta_len(p.lmax, p.nbins);
+  hipError_t e;
+  if (!p.accumulate &&
+      (e = launch_fill_double(zeta, int64_t(zlen) * ncat, 0.0, st)) != hipSuccess)
+    return hip_fail(e, "zeta clear");
+  const size_t pos_row = (p.pos_dtype == G3PCF_F32 ? 4 : 8) * 3;
+  int64_t total = 0;
+  // one catalogue after another in the same workspace, in stream order (no
+  // host synchronisation unless pairs_out asks for the counts)
+  for (int c = 0; c < ncat; ++c) {
+    g3pcf_problem q = p;
+    q.n = offsets[c + 1] - offsets[c];
+    if (q.n == 0) continue;
+    q.pos = static_cast<const char*>(p.pos) + size_t(offsets[c]) * pos_row;
+    q.w = p.w + offsets[c];
+    q.primary_mask = p.primary_mask ? p.primary_mask + offsets[c] : nullptr;
+    int64_t pairs_c = 0;
+    q.pairs_out = p.pairs_out ? &pairs_c : nullptr;
+    const Ws w = plan(q, 0);
+    if ((rc = check_workspace(w, ws, ws_bytes))) return rc;
+    {
+      StageScope sc(p.trace, G3PCF_STAGE_CELLS, st);
+      if ((rc = stage_catalogue(q, w, ws, st))) return rc;
+    }
+    if ((rc = forward_pairs(q, w, ws, zeta + zlen * size_t(c), q.n, nullptr, st))) return rc;
+    if ((rc = finish_pairs(q, w, ws, st))) return rc;
+    total += pairs_c;
+  }
+  if (p.pairs_out) *p.pairs_out = total;
+  return G3PCF_OK;
+}
+
 int g3pcf_backward(const g3pcf_problem* prob, const double* grad_zeta, double* grad_w, void* ws,
                    size_t ws_bytes, void* stream) {
   int rc = validate(prob);

@@ -242,3 +242,30 @@ def test_alm_store_checked_before_device_work(lib):
     assert lib.g3pcf_forward_regions(ctypes.byref(p), ctypes.c_void_p(0x5000), 4, zeta, ws, big,
                                      None) == _lib.EINVAL
     assert b"region" in lib.g3pcf_last_error()
+
+
+@pytest.mark.parametrize("ncat,offs", [
+    (0, [0]),                  # no catalogue
+    (2, None),                 # offsets missing
+    (2, [1, 50, 100]),         # does not start at 0
+    (2, [0, 60, 99]),          # does not end at n
+    (3, [0, 60, 40, 100]),     # decreasing
+])
+def test_batch_rejects_bad_offsets_before_device_work(lib, ncat, offs):
+    p = _problem(n=100)
+    arr = (ctypes.c_int64 * len(offs))(*offs) if offs is not None else None
+    rc = lib.g3pcf_forward_batch(ctypes.byref(p), ncat, arr, ctypes.c_void_p(0x3000),
+                                 ctypes.c_void_p(0x100000), 1 << 40, None)
+    assert rc == _lib.EINVAL
+
+
+def test_batch_rejects_alm_store_and_small_workspace(lib):
+    p = _problem(n=100)
+    arr = (ctypes.c_int64 * 3)(0, 40, 100)
+    p.alm, p.alm_bytes = 0x200000, 1 << 30
+    assert lib.g3pcf_forward_batch(ctypes.byref(p), 2, arr, ctypes.c_void_p(0x3000),
+                                   ctypes.c_void_p(0x100000), 1 << 40, None) == _lib.EINVAL
+    p = _problem(n=100)
+    need = _lib.workspace_bytes(p, 0)
+    assert lib.g3pcf_forward_batch(ctypes.byref(p), 2, arr, ctypes.c_void_p(0x3000),
+                                   ctypes.c_void_p(0x100000), need - 1, None) == _lib.EWORKSPACE
