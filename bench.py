@@ -36,11 +36,11 @@ PEAK = {  # MI355X published peaks
 # 11 adds/FMAs for m = 0 (21 flops), 110 FMAs for m >= 1 (220), the complex
 # chain (x - i y)^m (2 + 9 x 6 = 56) and z^n (9) = 306.
 FLOPS_PER_PAIR = {"cartesian": 572, "spin": 306}
-# Algorithmic flops per pair of the FP32 spin adjoint pair kernel: the
-# polynomial in (x - i y)^m T_n(z): T_n by recurrence (1 + 9 x 2 = 19), m = 0
-# (10 FMAs, 20), the chain (9 x 6 = 54), m >= 1 (90 FMAs, 180), the Re parts
-# (20 FMAs, 40), times the primary's weight (1) = 314.
-ADJ_FLOPS_PER_PAIR = {"spin": 314}
+# Algorithmic flops per pair of the FP32 adjoint pair kernel (either basis):
+# the polynomial in (x - i y)^m T_n(z): T_n by recurrence (1 + 9 x 2 = 19),
+# m = 0 (10 FMAs, 20), the chain (9 x 6 = 54), m >= 1 (90 FMAs, 180), the Re
+# parts (20 FMAs, 40), times the primary's weight (1) = 314.
+ADJ_FLOPS_PER_PAIR_FP32 = 314
 
 WORKLOADS = {
     "c1": "config1",
@@ -285,7 +285,7 @@ def main():
         adj_avg = sum(adj_launches) / len(adj_launches)
         adj_pps = pairs / (len(adj_launches) / args.steps) / (adj_avg * 1e-3)
         out["adjoint_kernel"] = {"avg_launch_ms": adj_avg, "pairs_per_s": adj_pps}
-        afpp = ADJ_FLOPS_PER_PAIR.get(args.basis) if args.precision != "fp64" else None
+        afpp = ADJ_FLOPS_PER_PAIR_FP32 if args.precision != "fp64" else None
         if afpp:
             out["adjoint_kernel"]["flops_per_pair"] = afpp
             out["adjoint_kernel"]["tflops"] = adj_pps * afpp / 1e12

@@ -79,7 +79,7 @@ typedef enum {
   G3PCF_BASIS_SPIN_T = 2     /* diagnostic only (g3pcf_conj_ylm_via_monomials),
                                 not a problem setting: (dx/r - i dy/r)^m T_n(dz/r)
                                 with Chebyshev polynomials T_n, the basis in which
-                                the FP32 spin adjoint evaluates its per-pair
+                                the FP32 adjoint evaluates its per-pair
                                 polynomial (no cancelling coefficients)          */
 } g3pcf_basis;
 

@@ -640,11 +640,12 @@ int g3pcf_backward(const g3pcf_problem* prob, const double* grad_zeta, double* g
   if ((rc = check_workspace(w, ws, ws_bytes))) return rc;
   if ((rc = check_alm(p, w))) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  // the FP32 spin adjoint evaluates its per-pair polynomial with Chebyshev
-  // polynomials of u_z (coefficients from the SPIN_T table)
-  const int adj_table = (p.basis == G3PCF_BASIS_SPIN && p.pair_prec == G3PCF_PREC_FP32)
-                            ? int(G3PCF_BASIS_SPIN_T)
-                            : int(p.basis);
+  // the FP32 adjoint (either basis) evaluates its per-pair polynomial in
+  // (x - i y)^m T_n(z) (coefficients from the SPIN_T table); the FP64
+  // adjoint in the forward's own monomial basis
+  const bool fp32 = (p.pair_prec == G3PCF_PREC_FP32);
+  const int adj_table = fp32 ? int(G3PCF_BASIS_SPIN_T) : int(p.basis);
+  const int adj_basis = fp32 ? int(G3PCF_BASIS_SPIN) : int(p.basis);
   if ((rc = ensure_tables(p.basis)) || (rc = ensure_tables(adj_table))) return rc;
   if (p.n == 0) {
     if (p.pairs_out) *p.pairs_out = 0;
@@ -699,7 +700,7 @@ int g3pcf_backward(const g3pcf_problem* prob, const double* grad_zeta, double* g
     j.p_begin = b0;
     j.p_count = a.p_count;
     j.lay = w.lay;
-    j.basis = p.basis;
+    j.basis = adj_basis;
     j.table = tab;
     j.gcoef = at<double>(ws, w.gcoef);
     j.grad_w = gsort;

@@ -18,7 +18,7 @@ constexpr int kTermsCart = (kDeg + 1) * (kDeg + 2) * (kDeg + 3) / 6;  // 286
 constexpr int kTermsSpin = (kDeg + 1) * (kDeg + 1);                   // 121 real sums
 // Conversion tables: G3PCF_BASIS_CARTESIAN, G3PCF_BASIS_SPIN and
 // G3PCF_BASIS_SPIN_T (the spin terms with T_n(u_z) in place of u_z^n; only the
-// FP32 spin adjoint uses it).
+// FP32 adjoint uses it, after a forward pass in either basis).
 constexpr int kConvTables = 3;
 // Internal "basis" of the pass that collects the degenerate (j = k) triangles:
 // per shell the sums w_j^2 P_n(u_z) of Legendre polynomials, n <= 2 kDeg.

@@ -440,7 +440,7 @@ struct SpinChunk {
   }
 };
 
-// Adjoint polynomial of the FP32 spin path: the sum over (m, n) of the
+// Adjoint polynomial of the FP32 path (either basis): the sum over (m, n) of the
 // coefficients times the Re / Im parts of (x - i y)^m T_n(z), with Chebyshev
 // polynomials T_n in place of z^n.  In this basis the coefficients of the
 // spherical harmonics do not cancel (those of z^n do, by two to three orders

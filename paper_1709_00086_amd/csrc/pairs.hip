@@ -90,7 +90,7 @@ struct RunEntry<double> {
 
 // ---------------------------------------------------------------- per-wave LDS
 // M holds the shell's reduced monomial sums (forward only).
-// FP32 spin adjoint: (secondary, term) pairs waiting for their atomic add.
+// FP32 adjoint: (secondary, term) pairs waiting for their atomic add.
 constexpr int kOutBuf = 8 * kWave;
 
 template <typename Real, bool ADJ, bool SPINT = false>
@@ -100,7 +100,7 @@ struct WaveLds {
   RunEntry<Real> run[kMaxRuns];
   V ring[kRing];               // (d_x, d_y, d_z, w) forward; (d_x, d_y, d_z, index) adjoint
   int ring_j[kRing];           // secondary index of a ring entry (when spilled)
-  // forward: the reduced sums (+1 padding slot); FP32 spin adjoint: the
+  // forward: the reduced sums (+1 padding slot); FP32 adjoint: the
   // shell's polynomial coefficients on their way into vector registers
   Real M[ADJ ? (SPINT ? kTermsSpin + 3 : 1) : kTermsCart + 1];
   int2 out[SPINT ? kOutBuf : 1];
@@ -242,7 +242,8 @@ struct Bin64 {
 // 512 / target per lane, so every accumulator chunk must fit.  The FP64 and
 // cartesian adjoints hold no accumulators: at four waves they spill a few
 // values outside their loops and hide more of their atomics' latency (5-11%
-// faster than three).  The FP32 spin adjoint holds its 121 coefficients in
+// faster than three).  The FP32 adjoint (the spin-basis instantiation, used
+// after a forward pass in either basis) holds its 121 coefficients in
 // vector registers, like the forward's 121 sums: three waves.
 template <typename Real, int BASIS, bool ADJOINT>
 struct Occ {
@@ -263,7 +264,7 @@ constexpr int n_chunks(ChunkList<C...>) {
 template <typename Real, int BASIS, bool ADJOINT>
 struct PairKernel {
   using V = typename V4<Real>::T;
-  // FP32 spin adjoint: Chebyshev-basis polynomial in FP32 (SpinTPoly)
+  // FP32 adjoint: Chebyshev-basis polynomial in FP32 (SpinTPoly)
   static constexpr bool kSpinT = Occ<Real, BASIS, ADJOINT>::kSpinT;
   using Lds = WaveLds<Real, ADJOINT, kSpinT>;
   static constexpr bool kF32 = std::is_same<Real, float>::value;
@@ -757,7 +758,7 @@ struct PairKernel {
       // the shell's coefficients, read through the scalar cache (uniform)
       const CoefPtr gc = (CoefPtr)(a.gcoef + (row * a.nbins + b) * kTerms);
       if constexpr (kSpinT) {
-        // FP32 spin: Chebyshev-basis coefficients, converted once per shell
+        // FP32: Chebyshev-basis coefficients, converted once per shell
         // and staged through LDS (one vector load per lane, then broadcast
         // reads) into vector registers; FP32 polynomial and FP32 atomics
         const double* gv = a.gcoef + (row * a.nbins + b) * kTerms;
@@ -988,7 +989,7 @@ struct PairKernel {
     if (lane < nd) a.A[row * a.lay.W + b * nd + lane] = double(W.M[lane]);
   }
 
-  // The buffered secondary terms of the FP32 spin adjoint into the FP32
+  // The buffered secondary terms of the FP32 adjoint into the FP32
   // gradient (n: a multiple of the wave size; index -1 marks an empty lane).
   static __device__ __forceinline__ void flush_terms(const PairArgs& a, Lds& W, int n) {
     wave_lds_fence();
@@ -999,22 +1000,18 @@ struct PairKernel {
     wave_lds_fence();
   }
 
-  // Adjoint for one pair per lane: the full polynomial sum_t g_t mono_t(u) in
-  // FP64 (its coefficients cancel strongly at l = 10).  The coefficients are
-  // the same for every lane, so they are read into scalar registers.
+  // FP64 adjoint for one pair per lane: the full polynomial sum_t g_t
+  // mono_t(u) in the forward's monomial basis, in FP64 (its coefficients
+  // cancel strongly at l = 10).  The coefficients are the same for every
+  // lane, so they are read into scalar registers.
   static __device__ __forceinline__ void scatter_one(const PairArgs& a, CoefPtr gc, Real ux,
                                                      Real uy, Real uz, int j, bool valid,
                                                      double w_prim) {
+    static_assert(!kF32, "the FP32 adjoint evaluates SpinTPoly");
     using Poly = std::conditional_t<BASIS == G3PCF_BASIS_SPIN, SpinChunk<double, 0, kDeg>,
                                     CartChunk<double, (1u << (kDeg + 1)) - 1>>;
     const double v = Poly::poly(double(ux), double(uy), double(uz), [&](int t) { return gc[t]; });
-    // the FP32 pair path also sums the secondary terms in FP32: one FP32
-    // atomic per pair (with FP64 atomics the kernel takes 11% longer)
-    if constexpr (kF32) {
-      if (valid) unsafeAtomicAdd(&a.grad_w32[j], float(w_prim * v));
-    } else {
-      if (valid) unsafeAtomicAdd(&a.grad_w[j], w_prim * v);
-    }
+    if (valid) unsafeAtomicAdd(&a.grad_w[j], w_prim * v);
   }
 };
 
@@ -1059,8 +1056,10 @@ hipError_t launch_pair_adjoint(const PairArgs& a, int fp64, int basis, hipStream
   if (fp64)
     return basis == G3PCF_BASIS_SPIN ? launch_one<double, G3PCF_BASIS_SPIN, true>(a, st)
                                      : launch_one<double, G3PCF_BASIS_CARTESIAN, true>(a, st);
-  return basis == G3PCF_BASIS_SPIN ? launch_one<float, G3PCF_BASIS_SPIN, true>(a, st)
-                                   : launch_one<float, G3PCF_BASIS_CARTESIAN, true>(a, st);
+  // The per-pair polynomial represents sum_lm H_lm conj(Y_lm(u)) whatever
+  // monomial basis the forward pass accumulated in: the FP32 adjoint always
+  // evaluates it in the spin-Chebyshev basis (coefficients from that table).
+  return launch_one<float, G3PCF_BASIS_SPIN, true>(a, st);
 }
 
 }  // namespace g3
