@@ -42,7 +42,7 @@ constexpr int kPairWaves = 4096;
 // accumulator chunks of a multi-chunk basis.
 constexpr int kSpillCap = 1 << 14;
 // Maximum pair-block (primaries whose a_lm rows are held at once).
-constexpr int kPairBlockMax = 131072;
+constexpr int kPairBlockMax = 524288;
 
 // Sparse monomial -> a_lm conversion table, one row per real output of a
 // shell.  Output o = (m, part, l) with part 0 = Re, 1 = Im (m >= 1 only).
