@@ -114,7 +114,9 @@ Ws plan(const g3pcf_problem& p, int backward) {
   w.degD = take(deg ? size_t(p.nbins) * (2 * p.lmax + 1) * 8 : 0);
   w.degP = take(deg ? deg_partial_doubles(w.PB, p.nbins, p.lmax) * 8 : 0);
   if (backward) {
-    const int T = (p.basis == G3PCF_BASIS_SPIN) ? kTermsSpin : kTermsCart;
+    // adjoint coefficients per primary and shell: the FP32 adjoint always
+    // takes the 121 spin-Chebyshev terms, the FP64 one the forward's basis
+    const int T = (p.basis == G3PCF_BASIS_SPIN || !fp64) ? kTermsSpin : kTermsCart;
     w.gcoef = take(size_t(w.PB) * p.nbins * T * 8);
     w.gsort = take(size_t(n) * 8);
     w.gsort32 = take(fp64 ? 0 : size_t(n) * 4);  // FP32 secondary terms (FP32 pair path)

@@ -150,3 +150,22 @@ def test_zeta_stage_sweep_across_blocks(dev):
         pe = (np.abs(z - z64)[big] / np.abs(z64)[big]).max()
         say(f"  zeta stage {zp}: max|dz|/max|z| = {e:.3e}, max per-entry rel = {pe:.3e}")
         assert e <= 1e-5
+
+
+def test_ragged_pair_blocks_add_up(dev):
+    """Config-2 catalogue, primaries split into 2^19 + 777 and the rest: one
+    side runs a full pair-block of 524,288 primaries plus a ragged one of 777,
+    the other a single ragged block; the two zetas add up to the zeta of all
+    primaries (two full blocks) in FP64, and their pair counts to its count."""
+    say("case ragged pair-blocks")
+    cat = catalogue("config2")
+    perm = np.random.default_rng(19).permutation(cat.n)
+    a = np.zeros(cat.n, dtype=np.uint8)
+    a[perm[: (1 << 19) + 777]] = 1
+    za, pa = run(cat, dev, "fp64", "spin", a)
+    zb, pb = run(cat, dev, "fp64", "spin", (1 - a).astype(np.uint8))
+    z64, p64 = run(cat, dev, "fp64", "spin")
+    assert pa + pb == p64
+    e = rel(za + zb, z64)
+    say(f"  ragged blocks additivity (fp64): {e:.3e}")
+    assert e <= 1e-12
