@@ -221,7 +221,7 @@ int g3pcf_forward_regions(const g3pcf_problem* prob, const int32_t* region, int 
 
 /* Forward pass over a batch of ncat catalogues of one geometry (randoms or
  * mocks sharing the box, shells, lmax, line of sight and precision), the
- * paper's downstream use (Sec. 6): catalogue c is the galaxies
+ * paper's downstream use (Sec. 6.1): catalogue c is the galaxies
  * [offsets[c], offsets[c+1]) of prob's arrays (positions, weights and, if set,
  * primary_mask), and its zeta goes to zeta + c * g3pcf_zeta_len, computed as
  * g3pcf_forward would for that catalogue alone (pairs never cross
