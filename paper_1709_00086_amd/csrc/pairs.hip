@@ -74,8 +74,10 @@ constexpr int kWavesPerBlock = 4;
 constexpr int kMaxRuns = 4 * kWave;  // runs of one chunk of 64 rows (<= 4 per row)
 constexpr int kRing = 2 * kWave;     // accepted pairs waiting for a full wave
 
-// A run of the table.  FP32 keeps the primary's position minus the run's
-// periodic image shift (the reference the candidates are measured from).
+// A run of the table: g0 is the cell-order slot of its first galaxy minus the
+// run's first virtual candidate index (so candidate c of the run is slot
+// g0 + c).  FP32 keeps the primary's position minus the run's periodic image
+// shift (the reference the candidates are measured from).
 template <typename Real>
 struct RunEntry;
 template <>
@@ -100,6 +102,7 @@ struct WaveLds {
   RunEntry<Real> run[kMaxRuns];
   V ring[kRing];               // (d_x, d_y, d_z, w) forward; (d_x, d_y, d_z, index) adjoint
   int ring_j[kRing];           // secondary index of a ring entry (when spilled)
+  int win[kWave];              // run starts inside the current candidate window
   // forward: the reduced sums (+1 padding slot); FP32 adjoint: the
   // shell's polynomial coefficients on their way into vector registers
   Real M[ADJ ? (SPINT ? kTermsSpin + 3 : 1) : kTermsCart + 1];
@@ -403,7 +406,7 @@ struct PairKernel {
       if (i < n_here) {
         W.pre[at + i] = v;
         RunEntry<Real> e;
-        e.g0 = g0v[i];
+        e.g0 = g0v[i] - v;  // galaxy slot of virtual candidate index c: e.g0 + c
         if constexpr (kF32) {
           e.rx = float(p[0] - kxv[i] * a.L[0]);
           e.ry = float(p[1] - ky * a.L[1]);
@@ -420,35 +423,33 @@ struct PairKernel {
   }
 
   // Candidate of each lane in the window [v0, v0 + 64) of the chunk's runs
-  // (lanes past the end repeat the last candidate).  kb is the run holding v0
-  // on entry and the run holding v0 + 63 on return.  The run starts are read
-  // from a register cache: lane i holds pre[kbase + i] (INT_MAX past the last
-  // run), reloaded only when a window may reach past the cached runs.
-  static __device__ __forceinline__ int map_window(const Lds& W, int nrun, int total, int v0,
-                                                   int& kb, int& kbase, int& prec, Real ref[3]) {
+  // (lanes past the end repeat the last candidate).  Windows come in order:
+  // kb is the run holding v0 - 1 on entry (-1 before the first window) and the
+  // run holding the window's last candidate on return.  The run starts are
+  // read from a register cache: lane i holds pre[kbase + i] (INT_MAX past the
+  // last run), kept at kbase <= kb + 1 and reloaded from kb + 1 when a window
+  // may reach past the cached runs.  Runs are never empty, so the starts that
+  // fall inside the window are distinct positions: they are marked in LDS,
+  // and a lane's run is kb plus the marks at or below its position.
+  static __device__ __forceinline__ int map_window(Lds& W, int nrun, int total, int v0, int& kb,
+                                                   int& kbase, int& prec, Real ref[3]) {
     const int lane = threadIdx.x % kWave;
     const int vc = min(v0 + lane, total - 1);
     const int vend = min(v0 + kWave - 1, total - 1);
-    // cached runs that start at or before the window's last candidate (the
-    // starts increase, so these are the lanes below `upto`)
-    int upto = __popcll(ballot(prec <= vend));
-    if (upto == kWave && kbase + kWave < nrun && kb > kbase) {
-      kbase = kb;
+    // all 64 cached runs start at or before the window's last candidate: the
+    // next run may too, so the cache moves up to the first run past kb
+    if (ballot(prec <= vend) == ~0ull && kbase + kWave < nrun && kb + 1 > kbase) {
+      kbase = kb + 1;
       prec = (kbase + lane < nrun) ? W.pre[kbase + lane] : INT_MAX;
-      upto = __popcll(ballot(prec <= vend));
     }
-    // runs kb .. kb + c - 1 overlap the window (at most 64 of them)
-    const int r0 = kb - kbase;
-    const int c = upto - r0;
-    int koff = 0;
-    int prek = __builtin_amdgcn_readlane(prec, r0);
-    for (int i = 1; i < c; ++i) {
-      const int s = __builtin_amdgcn_readlane(prec, r0 + i);
-      const bool ge = vc >= s;
-      koff += ge ? 1 : 0;
-      prek = ge ? s : prek;
-    }
-    const int k = kb + koff;
+    // LDS operations of one wave complete in order; the empty statements only
+    // keep the compiler from reordering the three accesses
+    W.win[lane] = 0;
+    asm volatile("" ::: "memory");
+    if (prec >= v0 && prec <= vend) W.win[prec - v0] = 1;
+    asm volatile("" ::: "memory");
+    const int f = W.win[lane];
+    const int k = kb + lanes_below(ballot(f != 0)) + f;
     kb = __builtin_amdgcn_readlane(k, kWave - 1);
     const RunEntry<Real> e = W.run[k];
     if constexpr (kF32) {
@@ -456,7 +457,7 @@ struct PairKernel {
       ref[1] = e.ry;
       ref[2] = e.rz;
     }
-    return e.g0 + (vc - prek);
+    return e.g0 + vc;
   }
 
   // Unit separation (rotated into the line-of-sight frame) of a ring entry.
@@ -527,7 +528,7 @@ struct PairKernel {
       int total = 0;
       const int nrun = build_runs(a, cs, P, r0sq, r1sq, c0, nyr, inv_nyr, rb, nrows, W, total);
       if (total == 0) continue;
-      int kb = 0, kbase = 0;
+      int kb = -1, kbase = 0;
       int prec = lane < nrun ? W.pre[lane] : INT_MAX;
       // bin one window and append its accepted pairs to the ring; consume a
       // full wave of pairs when there is one
