@@ -29,7 +29,8 @@ def build(force: bool = False, sanitize: bool = False) -> str:
         cmd = ["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math",
                "-fopenmp", "-shared", "-fPIC", SRC, "-o", out + ".tmp"]
         if sanitize:
-            cmd[1:1] = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-g"]
+            cmd[1:1] = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                        "-fno-omit-frame-pointer", "-g"]
         subprocess.check_call(cmd)
         os.replace(out + ".tmp", out)
     return out
@@ -38,7 +39,10 @@ def build(force: bool = False, sanitize: bool = False) -> str:
 def _load():
     global _lib
     if _lib is None:
-        lib = ctypes.CDLL(build())
+        # G3PCF_ORACLE_SANITIZED=1 loads the AddressSanitizer / UBSan build
+        # (the process must run with the ASan runtime preloaded)
+        san = os.environ.get("G3PCF_ORACLE_SANITIZED") == "1"
+        lib = ctypes.CDLL(build(sanitize=san))
         d = ctypes.c_double
         pd = ctypes.POINTER(ctypes.c_double)
         i64 = ctypes.c_int64

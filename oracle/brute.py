@@ -27,8 +27,11 @@ def _wrapped(cat):
 
 
 def _rodrigues_to_z(n):
-    """A rotation R with R n = z, built with Rodrigues' formula about n x z."""
+    """A rotation R with R n = z, built with Rodrigues' formula about n x z
+    (the identity for n = 0: a primary on the observer keeps the box frame)."""
     n = np.asarray(n, dtype=np.float64)
+    if not np.any(n):
+        return np.eye(3)
     n = n / np.linalg.norm(n)
     z = np.array([0.0, 0.0, 1.0])
     v = np.cross(n, z)

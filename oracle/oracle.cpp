@@ -138,24 +138,23 @@ struct Ctx {
     nlm = (p.lmax + 1) * (p.lmax + 2) / 2;
   }
 
-  // Frame rotation of primary i (identity in z mode).  Returns false if the
-  // primary sits on the observer.
-  bool frame(int64_t i, double R[3][3]) const {
-    if (p.los == 0) {
-      for (int r = 0; r < 3; ++r)
-        for (int c = 0; c < 3; ++c) R[r][c] = (r == c) ? 1.0 : 0.0;
-      return true;
-    }
+  // Frame rotation of primary i: identity in z mode, and also where the line
+  // of sight is undefined: a primary exactly on the observer, or one with a
+  // non-finite coordinate (which has no neighbours anyway).  The paper is
+  // silent on both; the box frame is the reading taken.
+  void frame(int64_t i, double R[3][3]) const {
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) R[r][c] = (r == c) ? 1.0 : 0.0;
+    if (p.los == 0) return;
     double d[3], nn = 0.0;
     for (int c = 0; c < 3; ++c) {
       d[c] = X[3 * i + c] - p.obs[c];
       nn += d[c] * d[c];
     }
     nn = std::sqrt(nn);
-    if (!(nn > 0.0)) return false;
+    if (!(nn > 0.0) || !std::isfinite(nn)) return;
     for (int c = 0; c < 3; ++c) d[c] /= nn;
     los_rotation(d, R);
-    return true;
   }
 
   // Visit every accepted secondary j of primary i: f(j, bin, u[3]).
@@ -230,7 +229,7 @@ void oracle_ylm(double ux, double uy, double uz, int lmax, double* out) {
 // both sides, so b1 = b2): their terms w_i w_j^2 conj(Y_lm(u_ij)) Y_l'm(u_ij)
 // are subtracted from the product of the a_lm (Sec. 3.1 writes zeta as that
 // product, which contains them).
-// Returns 0, or -1 on invalid arguments, -2 if a primary sits on the observer.
+// Returns 0, or -1 on invalid arguments.
 int oracle_zeta(int64_t n, const double* pos, const double* w, const double* L,
                 const double* lo, int periodic, const double* obs, double rmax, int nbins,
                 int lmax, int los, const uint8_t* mask, double* zeta, int64_t* pairs_out,
@@ -243,7 +242,6 @@ int oracle_zeta(int64_t n, const double* pos, const double* w, const double* L,
   if (nthreads < 1) nthreads = 1;
   std::vector<std::vector<double>> part(nthreads, std::vector<double>(zlen, 0.0));
   std::vector<int64_t> npart(nthreads, 0);
-  int err = 0;
   // Static contiguous split: deterministic for a given thread count.
 #pragma omp parallel num_threads(nthreads)
   {
@@ -255,11 +253,7 @@ int oracle_zeta(int64_t n, const double* pos, const double* w, const double* L,
     for (int64_t i = i0; i < i1; ++i) {
       if (!ctx.is_primary(i)) continue;
       double R[3][3];
-      if (!ctx.frame(i, R)) {
-#pragma omp atomic write
-        err = -2;
-        continue;
-      }
+      ctx.frame(i, R);
       npart[t] += ctx.alm(i, R, a, y);
       const double wi = w[i];
       for (int m = 0; m <= lmax; ++m)
@@ -290,7 +284,6 @@ int oracle_zeta(int64_t n, const double* pos, const double* w, const double* L,
       }
     }
   }
-  if (err) return err;
   std::memset(zeta, 0, zlen * sizeof(double));
   int64_t np = 0;
   for (int t = 0; t < nthreads; ++t) {
@@ -320,7 +313,6 @@ int oracle_grad(int64_t n, const double* pos, const double* w, const double* L,
   if (nthreads < 1) nthreads = 1;
   const int nlm = ctx.nlm;
   std::vector<std::vector<double>> part(nthreads, std::vector<double>(size_t(n), 0.0));
-  int err = 0;
   auto G = [&](int m, int l, int lp, int b1, int b2) {
     const double* q = c + zidx(lmax, nbins, m, l, lp, b1, b2);
     return cd(q[0], q[1]);
@@ -336,11 +328,7 @@ int oracle_grad(int64_t n, const double* pos, const double* w, const double* L,
     for (int64_t i = i0; i < i1; ++i) {
       if (!ctx.is_primary(i)) continue;
       double R[3][3];
-      if (!ctx.frame(i, R)) {
-#pragma omp atomic write
-        err = -2;
-        continue;
-      }
+      ctx.frame(i, R);
       ctx.alm(i, R, a, y);
       auto A = [&](int b, int l, int m) { return a[size_t(b) * nlm + lm_index(l, m)]; };
       // primary term
@@ -381,7 +369,6 @@ int oracle_grad(int64_t n, const double* pos, const double* w, const double* L,
       });
     }
   }
-  if (err) return err;
   std::memset(grad, 0, size_t(n) * sizeof(double));
   for (int t = 0; t < nthreads; ++t)
     for (int64_t k = 0; k < n; ++k) grad[k] += part[t][k];

@@ -85,6 +85,59 @@ def test_observer_mode_independent_of_azimuthal_frame():
     assert rel(z, zb) <= 1e-12
 
 
+def test_primary_on_the_observer_keeps_the_box_frame():
+    """A primary exactly on the observer has no line of sight; it keeps the box
+    frame (identity).  Its part of zeta then equals the z-mode part, and the
+    whole zeta still matches the triplet brute force (which builds its frames
+    independently)."""
+    import dataclasses
+    cat = C.tiny(**CASES[2])
+    obs = tuple(float(v) for v in cat.pos[5])
+    cat = dataclasses.replace(cat, observer=obs)
+    z = oracle.zeta(cat)
+    assert rel(z, brute.zeta_triplets(cat)) <= 1e-12
+    only = np.zeros(cat.n, np.uint8)
+    only[5] = 1
+    z_obs = oracle.zeta(cat, primary_mask=only)
+    z_z = oracle.zeta(dataclasses.replace(cat, los="z"), primary_mask=only)
+    assert np.abs(z_obs).max() > 0
+    assert np.array_equal(z_obs, z_z)
+    # the gradient takes the same frame: central differences of the oracle
+    c = np.random.default_rng(3).standard_normal(C.zeta_shape(cat.lmax, cat.nbins))
+    g = oracle.grad(cat, c)
+    h = 1e-3
+    for k in (5, 7):
+        wp = cat.w.copy(); wp[k] += h
+        wm = cat.w.copy(); wm[k] -= h
+        fd = ((oracle.zeta(dataclasses.replace(cat, w=wp)) * c).sum()
+              - (oracle.zeta(dataclasses.replace(cat, w=wm)) * c).sum()) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-9 * max(1.0, abs(g[k]))
+
+
+@pytest.mark.parametrize("case", [CASES[0], CASES[2]])
+def test_non_finite_position_has_no_pairs(case):
+    """A galaxy with a non-finite coordinate has no accepted separation: zeta
+    and the other weights' gradient equal those of the catalogue without it,
+    and its own gradient is zero."""
+    import dataclasses
+    cat = C.tiny(**case)
+    bad = cat.pos.copy()
+    bad[3, 1] = np.nan
+    bad[9, 2] = np.inf
+    with_bad = dataclasses.replace(cat, pos=bad)
+    keep = np.setdiff1d(np.arange(cat.n), [3, 9])
+    without = cat.subset(keep)
+    z, pairs = oracle.zeta(with_bad, return_pairs=True)
+    z0, pairs0 = oracle.zeta(without, return_pairs=True)
+    assert pairs == pairs0
+    assert rel(z, z0) <= 1e-14
+    c = np.random.default_rng(4).standard_normal(C.zeta_shape(cat.lmax, cat.nbins))
+    g = oracle.grad(with_bad, c)
+    g0 = oracle.grad(without, c)
+    assert g[3] == 0.0 and g[9] == 0.0
+    assert np.abs(g[keep] - g0).max() <= 1e-13 * np.abs(g0).max()
+
+
 # ---------------------------------------------------------------- pair counts
 @pytest.mark.parametrize("periodic", [True, False])
 def test_monopole_equals_kdtree_pair_counts(periodic):
