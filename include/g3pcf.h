@@ -74,13 +74,18 @@ typedef enum { G3PCF_F32 = 0, G3PCF_F64 = 1 } g3pcf_dtype;
 typedef enum {
   G3PCF_BASIS_CARTESIAN = 0, /* the paper's monomials (dx/r)^k (dy/r)^p (dz/r)^q,
                                 k+p+q <= 10: 286 sums per shell (eq. 1)          */
-  G3PCF_BASIS_SPIN = 1,      /* (dx/r - i dy/r)^m (dz/r)^n, m+n <= 10: 121 real
-                                sums per shell; the same zeta with fewer FMAs    */
+  G3PCF_BASIS_SPIN = 1,      /* (dx/r - i dy/r)^m T_n(dz/r), m+n <= 10, with the
+                                Chebyshev polynomials T_n: 121 real sums per
+                                shell; the same zeta with fewer FMAs.  T_n in
+                                place of the powers (dz/r)^n (the same span)
+                                keeps the conversion to Y_lm free of the
+                                cancellation that costs FP32 sums up to three
+                                digits at l = 10                                 */
   G3PCF_BASIS_SPIN_T = 2     /* diagnostic only (g3pcf_conj_ylm_via_monomials),
-                                not a problem setting: (dx/r - i dy/r)^m T_n(dz/r)
-                                with Chebyshev polynomials T_n, the basis in which
-                                the FP32 adjoint evaluates its per-pair
-                                polynomial (no cancelling coefficients)          */
+                                not a problem setting: the table of the spin
+                                basis above, (dx/r - i dy/r)^m T_n(dz/r); with
+                                G3PCF_BASIS_SPIN the diagnostic evaluates the
+                                plain powers (dx/r - i dy/r)^m (dz/r)^n instead  */
 } g3pcf_basis;
 
 /* Stages reported by a trace (see g3pcf_trace_create). */
@@ -274,9 +279,10 @@ int g3pcf_degenerate_term(int lmax, double uz, double* out);
 const char* g3pcf_last_error(void);
 
 /* Diagnostic, host only, no device use: evaluates the library's own
- * monomial-sum -> a_lm conversion (the same coefficient table the pair kernels
- * use) for a single unit vector u with unit weight, i.e. conj(Y_lm(u)) as the
- * pair stage represents it.  out: HOST array of (lmax+1)(lmax+2) doubles,
+ * monomial-sum -> a_lm conversion (a coefficient table the pair kernels use:
+ * G3PCF_BASIS_CARTESIAN, or G3PCF_BASIS_SPIN_T for the spin basis; or the
+ * spin basis in plain powers, G3PCF_BASIS_SPIN) for a single unit vector u
+ * with unit weight, i.e. conj(Y_lm(u)) as the pair stage represents it.  out: HOST array of (lmax+1)(lmax+2) doubles,
  * (re, im) pairs in triangular order (l(l+1)/2 + m), 0 <= m <= l <= lmax.
  * Returns G3PCF_OK or G3PCF_EINVAL (unknown basis, lmax outside 0..10, NULL). */
 int g3pcf_conj_ylm_via_monomials(int basis, int lmax, double ux, double uy, double uz,

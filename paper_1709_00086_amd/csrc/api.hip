@@ -61,8 +61,8 @@ constexpr size_t kCountersBytes = 1024;
 size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Ws {
-  size_t pos4, tmp4, cid, perm, tmp_perm, wsort, cell_start, cell_count, flags, plist, scan,
-      counters, spill, A, C, ops, gcoef, gsort, gsort32, mht, hrows, degD, degP;
+  size_t pos4, tmp4, cid, perm, tmp_perm, rkey, rhist, wsort, cell_start, cell_count, flags,
+      plist, scan, counters, spill, A, C, ops, gcoef, gsort, gsort32, mht, hrows, degD, degP;
   size_t scan_bytes;
   size_t total;
   int64_t PB;   // primaries per pair-block
@@ -72,7 +72,11 @@ struct Ws {
   RowLayout lay;
 };
 
-Ws plan(const g3pcf_problem& p, int backward) {
+// Workspace layout.  pb_max caps the primaries of a pair-block (the a_lm rows
+// held at once); spill = false leaves out the spill lists (a multi-chunk basis
+// then repeats its search per chunk).
+Ws plan(const g3pcf_problem& p, int backward, int64_t pb_max = kPairBlockMax,
+        bool spill = true) {
   Ws w{};
   const int64_t n = p.n;
   const int fp64 = (p.pair_prec == G3PCF_PREC_FP64);
@@ -80,9 +84,10 @@ Ws plan(const g3pcf_problem& p, int backward) {
   w.grid = make_grid(p);
   w.lay = make_layout(p.lmax, p.nbins);
   const int64_t ncell = w.grid.ncell;
-  w.PB = std::max<int64_t>(1, std::min<int64_t>(n, kPairBlockMax));
+  w.PB = std::max<int64_t>(1, std::min<int64_t>(n, pb_max));
   w.Kp = ((std::min<int64_t>(kZetaBlock, w.PB) + 31) / 32) * 32;
-  w.scan_bytes = scan_tmp_bytes(std::max<int64_t>(ncell + 1, n + 1));
+  const int64_t nhist = int64_t(radix_hist_ints(n));
+  w.scan_bytes = scan_tmp_bytes(std::max<int64_t>(std::max<int64_t>(ncell + 1, n + 1), nhist));
   size_t at = 0;
   auto take = [&](size_t bytes) {
     const size_t o = at;
@@ -94,6 +99,8 @@ Ws plan(const g3pcf_problem& p, int backward) {
   w.cid = take(size_t(n) * 4);
   w.perm = take(size_t(n) * 4);
   w.tmp_perm = take(size_t(n) * 4);
+  w.rkey = take(size_t(n) * 4);
+  w.rhist = take(size_t(2 * nhist) * 4);
   w.wsort = take(size_t(n) * 8);
   w.cell_start = take(size_t(ncell + 1) * 4);
   w.cell_count = take(size_t(ncell + 1) * 4);
@@ -102,11 +109,11 @@ Ws plan(const g3pcf_problem& p, int backward) {
   w.scan = take(w.scan_bytes);
   w.counters = take(kCountersBytes);
   // per-wave spill lists for bases accumulated in several register chunks
-  const bool multi = fp64 || p.basis == G3PCF_BASIS_CARTESIAN;
+  const bool multi = spill && (fp64 || p.basis == G3PCF_BASIS_CARTESIAN);
   w.spill = take(multi ? size_t(kPairWaves) * kSpillCap * 4 : 0);
   w.spill_cap = multi ? kSpillCap : 0;
   w.A = take(size_t(w.PB) * w.lay.W * 8);
-  w.C = take(zeta_partial_doubles(w.lay) * 8);
+  w.C = take(zeta_partial_doubles(w.lay, w.PB) * 8);
   w.ops = (!backward && p.zeta_prec == G3PCF_PREC_BF16X3) ? take(size_t(6) * w.lay.W * w.Kp * 2)
                                                            : take(0);
   // degenerate triangles: per-shell Legendre sums and their per-workgroup partials
@@ -201,11 +208,20 @@ static_assert(sizeof(Counters) <= kCountersBytes, "counters block");
 // Stages shared by forward and backward: cell list and primary list.
 int stage_catalogue(const g3pcf_problem& p, const Ws& w, void* ws, hipStream_t st) {
   const int fp64 = (p.pair_prec == G3PCF_PREC_FP64);
-  hipError_t e = launch_cells(p, w.grid, at<void>(ws, w.pos4), at<int>(ws, w.cell_start),
-                              at<int>(ws, w.cell_count), at<int>(ws, w.cid), at<int>(ws, w.perm),
-                              at<double>(ws, w.wsort), at<void>(ws, w.tmp4),
-                              at<int>(ws, w.tmp_perm), nullptr, at<void>(ws, w.scan),
-                              w.scan_bytes, fp64, st);
+  CellBufs b{};
+  b.pos4 = at<void>(ws, w.pos4);
+  b.stage4 = at<void>(ws, w.tmp4);
+  b.cell_start = at<int>(ws, w.cell_start);
+  b.cell_count = at<int>(ws, w.cell_count);
+  b.key_a = at<int>(ws, w.cid);
+  b.key_b = at<int>(ws, w.rkey);
+  b.val_a = at<int>(ws, w.tmp_perm);
+  b.perm = at<int>(ws, w.perm);
+  b.hist = at<int>(ws, w.rhist);
+  b.wsort = at<double>(ws, w.wsort);
+  b.scan_tmp = at<void>(ws, w.scan);
+  b.scan_bytes = w.scan_bytes;
+  hipError_t e = launch_cells(p, w.grid, b, fp64, st);
   if (e != hipSuccess) return hip_fail(e, "cell list");
   Counters* c = at<Counters>(ws, w.counters);
   e = launch_fill_int(reinterpret_cast<int*>(c), sizeof(Counters) / 4, 0, st);
@@ -334,7 +350,7 @@ hipError_t fingerprint(const g3pcf_problem& p, const Ws& w, void* ws, unsigned l
 }
 
 int forward_tables(const g3pcf_problem& p) {
-  int rc = ensure_tables(p.basis);
+  int rc = ensure_tables(conv_table_of(p.basis));
   if (!rc && p.distinct) rc = ensure_tables(kBasisDeg);
   return rc;
 }
@@ -414,6 +430,35 @@ int finish_pairs(const g3pcf_problem& p, const Ws& w, void* ws, hipStream_t st,
   *p.pairs_out = (int64_t)host;
   return G3PCF_OK;
 }
+
+// The forward pass in a workspace laid out by `w` (already checked).
+int forward_run(const g3pcf_problem& p, const Ws& w, double* zeta, void* ws, hipStream_t st) {
+  int rc;
+  if (p.alm && p.distinct)
+    return fail(G3PCF_EINVAL, "alm store with distinct = 1 (the adjoint does not cover it)");
+  if ((rc = check_alm(p, w))) return rc;
+  if ((rc = forward_tables(p))) return rc;
+  const size_t zlen = g3pcf_zeta_len(p.lmax, p.nbins);
+  hipError_t e;
+  if (!p.accumulate && (e = launch_fill_double(zeta, int64_t(zlen), 0.0, st)) != hipSuccess)
+    return hip_fail(e, "zeta clear");
+  if (p.n == 0) {
+    if (p.alm && (e = launch_fill_int(static_cast<int*>(p.alm), 2, 0, st)) != hipSuccess)
+      return hip_fail(e, "alm store header");
+    if (p.pairs_out) *p.pairs_out = 0;
+    return G3PCF_OK;
+  }
+  {
+    StageScope sc(p.trace, G3PCF_STAGE_CELLS, st);
+    if ((rc = stage_catalogue(p, w, ws, st))) return rc;
+    if (p.alm && (e = fingerprint(p, w, ws, static_cast<unsigned long long*>(p.alm), st)) !=
+                     hipSuccess)
+      return hip_fail(e, "alm store fingerprint");
+  }
+  if ((rc = forward_pairs(p, w, ws, zeta, p.n, p.alm ? alm_rows(p) : nullptr, st))) return rc;
+  return finish_pairs(p, w, ws, st);
+}
+
 
 }  // namespace
 }  // namespace g3
@@ -505,33 +550,9 @@ int g3pcf_forward(const g3pcf_problem* prob, double* zeta, void* ws, size_t ws_b
   int rc = validate(prob);
   if (rc) return rc;
   if (!zeta) return fail(G3PCF_EINVAL, "zeta is NULL");
-  const g3pcf_problem& p = *prob;
-  const Ws w = plan(p, 0);
+  const Ws w = plan(*prob, 0);
   if ((rc = check_workspace(w, ws, ws_bytes))) return rc;
-  if (p.alm && p.distinct)
-    return fail(G3PCF_EINVAL, "alm store with distinct = 1 (the adjoint does not cover it)");
-  if ((rc = check_alm(p, w))) return rc;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  if ((rc = forward_tables(p))) return rc;
-  const size_t zlen = g3pcf_zeta_len(p.lmax, p.nbins);
-  hipError_t e;
-  if (!p.accumulate && (e = launch_fill_double(zeta, int64_t(zlen), 0.0, st)) != hipSuccess)
-    return hip_fail(e, "zeta clear");
-  if (p.n == 0) {
-    if (p.alm && (e = launch_fill_int(static_cast<int*>(p.alm), 2, 0, st)) != hipSuccess)
-      return hip_fail(e, "alm store header");
-    if (p.pairs_out) *p.pairs_out = 0;
-    return G3PCF_OK;
-  }
-  {
-    StageScope sc(p.trace, G3PCF_STAGE_CELLS, st);
-    if ((rc = stage_catalogue(p, w, ws, st))) return rc;
-    if (p.alm && (e = fingerprint(p, w, ws, static_cast<unsigned long long*>(p.alm), st)) !=
-                     hipSuccess)
-      return hip_fail(e, "alm store fingerprint");
-  }
-  if ((rc = forward_pairs(p, w, ws, zeta, p.n, p.alm ? alm_rows(p) : nullptr, st))) return rc;
-  return finish_pairs(p, w, ws, st);
+  return forward_run(*prob, w, zeta, ws, static_cast<hipStream_t>(stream));
 }
 
 int g3pcf_forward_regions(const g3pcf_problem* prob, const int32_t* region, int nregions,
@@ -643,12 +664,13 @@ int g3pcf_backward(const g3pcf_problem* prob, const double* grad_zeta, double* g
   if ((rc = check_alm(p, w))) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
   // the FP32 adjoint (either basis) evaluates its per-pair polynomial in
-  // (x - i y)^m T_n(z) (coefficients from the SPIN_T table); the FP64
-  // adjoint in the forward's own monomial basis
+  // (x - i y)^m T_n(z) (coefficients from the spin-Chebyshev table); the
+  // FP64 adjoint in the forward's own basis
   const bool fp32 = (p.pair_prec == G3PCF_PREC_FP32);
-  const int adj_table = fp32 ? int(G3PCF_BASIS_SPIN_T) : int(p.basis);
+  const int adj_table = fp32 ? int(G3PCF_BASIS_SPIN_T) : conv_table_of(p.basis);
   const int adj_basis = fp32 ? int(G3PCF_BASIS_SPIN) : int(p.basis);
-  if ((rc = ensure_tables(p.basis)) || (rc = ensure_tables(adj_table))) return rc;
+  if ((rc = ensure_tables(conv_table_of(p.basis))) || (rc = ensure_tables(adj_table)))
+    return rc;
   if (p.n == 0) {
     if (p.pairs_out) *p.pairs_out = 0;
     return G3PCF_OK;

@@ -1,5 +1,5 @@
-// Catalogue staging: wrap, cell assignment, counting sort into cell order,
-// deterministic order inside every cell, and the compacted primary list.
+// Catalogue staging: wrap, cell assignment, a stable sort into cell order
+// (members of a cell in input order), and the compacted primary list.
 //
 // The paper keeps its galaxies in a node-local k-d tree for the range search
 // (Algorithm 1, "search node-local k-d tree").  On the GPU a uniform cell grid
@@ -45,10 +45,13 @@ struct GridDev {
   int periodic;
 };
 
+// Cell along one axis; coordinates outside the box (open boxes) go to the
+// edge cells, and a non-finite coordinate to cell 0 (such a galaxy is never
+// accepted as a secondary and has no neighbours as a primary).
 __device__ inline int cell_axis(double x, double lo, double inv_s, int nc) {
-  double f = floor((x - lo) * inv_s);
-  int c = (f < 0.0) ? 0 : (f >= double(nc) ? nc - 1 : int(f));
-  return c;
+  const double f = floor((x - lo) * inv_s);
+  if (!(f >= 0.0)) return 0;
+  return f >= double(nc) ? nc - 1 : int(f);
 }
 
 // Wrap (periodic), convert to the compute precision and assign a cell.
@@ -86,38 +89,100 @@ __global__ void k_assign(const In* __restrict__ pos, const double* __restrict__ 
   atomicAdd(&count[c], 1);
 }
 
-template <typename V4>
-__global__ void k_scatter(const V4* __restrict__ in4, const int* __restrict__ cid, int64_t n,
-                          const int* __restrict__ cell_start, int* __restrict__ cursor,
-                          V4* __restrict__ out4, int* __restrict__ out_perm) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int c = cid[i];
-  const int slot = cell_start[c] + atomicAdd(&cursor[c], 1);
-  out4[slot] = in4[i];
-  out_perm[slot] = int(i);
+// ---- stable LSD radix sort of the cell ids (values: original indices) ----
+// The galaxies come in input order, so a stable sort by cell id leaves every
+// cell's members in increasing input order: the cell list is deterministic
+// whatever the data (no atomics decide an order, and a crowded cell costs no
+// more than a sparse one).  Digits of kRadixBits bits; each pass counts the
+// digits of every tile of kRadixTile keys, scans the counts digit-major across
+// tiles, and scatters each tile in order.
+constexpr int kRadixBits = 8;
+constexpr int kRadixDigits = 1 << kRadixBits;
+constexpr int kRadixThreads = 256;
+constexpr int kRadixRounds = 8;
+constexpr int kRadixTile = kRadixThreads * kRadixRounds;
+constexpr int kRadixWaves = kRadixThreads / kWave;
+
+__global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const int* __restrict__ keys,
+                                                              int64_t n, int shift, int ntiles,
+                                                              int* __restrict__ hist) {
+  __shared__ int cnt[kRadixDigits];
+  for (int d = threadIdx.x; d < kRadixDigits; d += kRadixThreads) cnt[d] = 0;
+  __syncthreads();
+  const int64_t base = int64_t(blockIdx.x) * kRadixTile;
+  for (int k = 0; k < kRadixRounds; ++k) {
+    const int64_t e = base + k * kRadixThreads + threadIdx.x;
+    if (e < n) atomicAdd(&cnt[(keys[e] >> shift) & (kRadixDigits - 1)], 1);
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d < kRadixDigits; d += kRadixThreads)
+    hist[int64_t(d) * ntiles + blockIdx.x] = cnt[d];
 }
 
-// One wave per cell: order the members by original index so the whole
-// pipeline is deterministic (the scatter's atomics are not).
-template <typename V4>
-__global__ void k_cell_order(const V4* __restrict__ in4, const int* __restrict__ in_perm,
-                             const int* __restrict__ cell_start, int64_t ncell,
-                             const double* __restrict__ w, V4* __restrict__ out4,
-                             int* __restrict__ perm, double* __restrict__ wsort) {
-  const int64_t c = int64_t(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
-  const int lane = threadIdx.x % kWave;
-  if (c >= ncell) return;
-  const int s0 = cell_start[c], s1 = cell_start[c + 1];
-  for (int a = s0 + lane; a < s1; a += kWave) {
-    const int pa = in_perm[a];
-    int rank = 0;
-    for (int b = s0; b < s1; ++b) rank += (in_perm[b] < pa) ? 1 : 0;
-    const int dst = s0 + rank;
-    out4[dst] = in4[a];
-    perm[dst] = pa;
-    wsort[dst] = w[pa];
+// keys_in / vals_in (vals_in NULL: the value is the key's own index) into
+// keys_out (NULL: not written) / vals_out at the scanned offsets.  Within a
+// round of kRadixThreads keys, a key's rank among the keys of its wave with
+// the same digit comes from eight ballots; the waves' counts per digit give
+// the offsets across waves, and `base` carries each digit's running offset
+// from round to round.
+__global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(
+    const int* __restrict__ keys_in, const int* __restrict__ vals_in, int64_t n, int shift,
+    int ntiles, const int* __restrict__ offs, int* __restrict__ keys_out,
+    int* __restrict__ vals_out) {
+  __shared__ int base[kRadixDigits];
+  __shared__ int wcnt[kRadixWaves][kRadixDigits];
+  for (int d = threadIdx.x; d < kRadixDigits; d += kRadixThreads) {
+    base[d] = offs[int64_t(d) * ntiles + blockIdx.x];
+    for (int w = 0; w < kRadixWaves; ++w) wcnt[w][d] = 0;
   }
+  __syncthreads();
+  const int wave = threadIdx.x / kWave;
+  const int64_t tile0 = int64_t(blockIdx.x) * kRadixTile;
+  for (int k = 0; k < kRadixRounds; ++k) {
+    const int64_t e = tile0 + k * kRadixThreads + threadIdx.x;
+    const bool valid = e < n;
+    const int key = valid ? keys_in[e] : 0;
+    const int val = valid ? (vals_in ? vals_in[e] : int(e)) : 0;
+    const int d = (key >> shift) & (kRadixDigits - 1);
+    unsigned long long peers = __builtin_amdgcn_ballot_w64(valid);
+    for (int bit = 0; bit < kRadixBits; ++bit) {
+      const bool on = (d >> bit) & 1;
+      const unsigned long long b = __builtin_amdgcn_ballot_w64(on);
+      peers &= on ? b : ~b;
+    }
+    const int rank = __builtin_amdgcn_mbcnt_hi(unsigned(peers >> 32),
+                                               __builtin_amdgcn_mbcnt_lo(unsigned(peers), 0));
+    if (valid && rank == 0) wcnt[wave][d] = __popcll(peers);
+    __syncthreads();
+    if (valid) {
+      int off = base[d] + rank;
+      for (int w = 0; w < wave; ++w) off += wcnt[w][d];
+      if (keys_out) keys_out[off] = key;
+      vals_out[off] = val;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < kRadixDigits; t += kRadixThreads) {
+      int add = 0;
+      for (int w = 0; w < kRadixWaves; ++w) {
+        add += wcnt[w][t];
+        wcnt[w][t] = 0;
+      }
+      base[t] += add;
+    }
+    __syncthreads();
+  }
+}
+
+// Cell-order arrays from the sorted original indices.
+template <typename V4>
+__global__ void k_gather_sorted(const V4* __restrict__ in4, const int* __restrict__ perm,
+                                int64_t n, const double* __restrict__ w,
+                                V4* __restrict__ out4, double* __restrict__ wsort) {
+  const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int i = perm[s];
+  out4[s] = in4[i];
+  wsort[s] = w[i];
 }
 
 // primary flag of the galaxy in cell-order slot s: in the mask (if any) and,
@@ -331,10 +396,13 @@ Grid make_grid(const g3pcf_problem& p) {
   return g;
 }
 
-hipError_t launch_cells(const g3pcf_problem& p, const Grid& g, void* pos4, int* cell_start,
-                        int* cell_count, int* cid, int* perm, double* wsort, void* tmp4,
-                        int* tmp_perm, double* /*tmp_w*/, void* scan_tmp,
-                        size_t scan_tmp_bytes_, int fp64, hipStream_t st) {
+size_t radix_hist_ints(int64_t n) {
+  const int64_t ntiles = std::max<int64_t>(1, (n + kRadixTile - 1) / kRadixTile);
+  return size_t(ntiles) * kRadixDigits;
+}
+
+hipError_t launch_cells(const g3pcf_problem& p, const Grid& g, const CellBufs& b, int fp64,
+                        hipStream_t st) {
   const int64_t n = p.n;
   GridDev gd;
   for (int a = 0; a < 3; ++a) {
@@ -344,52 +412,70 @@ hipError_t launch_cells(const g3pcf_problem& p, const Grid& g, void* pos4, int* 
     gd.L[a] = g.L[a];
   }
   gd.periodic = g.periodic;
-  hipError_t e = launch_fill_int(cell_count, g.ncell + 1, 0, st);
+  hipError_t e = launch_fill_int(b.cell_count, g.ncell + 1, 0, st);
   if (e != hipSuccess) return e;
+  if (n == 0) return launch_fill_int(b.cell_start, g.ncell + 1, 0, st);
   const unsigned nb = blocks_for(n, 256);
-  // pos4 holds the staged (original order) values first; the final sorted
-  // values end up in pos4 as well, with tmp4 as the intermediate.
+  // staged values (input order) into stage4, the cell id of every galaxy
+  // into key_a, and the cell counts
   if (fp64) {
     if (p.pos_dtype == G3PCF_F64)
       hipLaunchKernelGGL((k_assign<double, double>), dim3(nb), dim3(256), 0, st,
                          static_cast<const double*>(p.pos), p.w, n, gd,
-                         static_cast<double4*>(pos4), cid, cell_count);
+                         static_cast<double4*>(b.stage4), b.key_a, b.cell_count);
     else
       hipLaunchKernelGGL((k_assign<double, float>), dim3(nb), dim3(256), 0, st,
                          static_cast<const float*>(p.pos), p.w, n, gd,
-                         static_cast<double4*>(pos4), cid, cell_count);
+                         static_cast<double4*>(b.stage4), b.key_a, b.cell_count);
   } else {
     if (p.pos_dtype == G3PCF_F64)
       hipLaunchKernelGGL((k_assign<float, double>), dim3(nb), dim3(256), 0, st,
                          static_cast<const double*>(p.pos), p.w, n, gd,
-                         static_cast<float4*>(pos4), cid, cell_count);
+                         static_cast<float4*>(b.stage4), b.key_a, b.cell_count);
     else
       hipLaunchKernelGGL((k_assign<float, float>), dim3(nb), dim3(256), 0, st,
                          static_cast<const float*>(p.pos), p.w, n, gd,
-                         static_cast<float4*>(pos4), cid, cell_count);
+                         static_cast<float4*>(b.stage4), b.key_a, b.cell_count);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // cell_start = exclusive scan of the counts (ncell + 1 entries, last = n)
-  if ((e = launch_scan(cell_count, cell_start, g.ncell + 1, scan_tmp, scan_tmp_bytes_, st)) !=
+  if ((e = launch_scan(b.cell_count, b.cell_start, g.ncell + 1, b.scan_tmp, b.scan_bytes, st)) !=
       hipSuccess)
     return e;
-  if ((e = launch_fill_int(cell_count, g.ncell + 1, 0, st)) != hipSuccess) return e;
-  const unsigned nbc = blocks_for(g.ncell, 256 / kWave);
-  if (fp64) {
-    hipLaunchKernelGGL((k_scatter<double4>), dim3(nb), dim3(256), 0, st,
-                       static_cast<const double4*>(pos4), cid, n, cell_start, cell_count,
-                       static_cast<double4*>(tmp4), tmp_perm);
-    hipLaunchKernelGGL((k_cell_order<double4>), dim3(nbc), dim3(256), 0, st,
-                       static_cast<const double4*>(tmp4), tmp_perm, cell_start, g.ncell, p.w,
-                       static_cast<double4*>(pos4), perm, wsort);
-  } else {
-    hipLaunchKernelGGL((k_scatter<float4>), dim3(nb), dim3(256), 0, st,
-                       static_cast<const float4*>(pos4), cid, n, cell_start, cell_count,
-                       static_cast<float4*>(tmp4), tmp_perm);
-    hipLaunchKernelGGL((k_cell_order<float4>), dim3(nbc), dim3(256), 0, st,
-                       static_cast<const float4*>(tmp4), tmp_perm, cell_start, g.ncell, p.w,
-                       static_cast<float4*>(pos4), perm, wsort);
+  // perm = input indices sorted stably by cell id
+  int bits = 0;
+  while ((int64_t(1) << bits) < g.ncell) ++bits;
+  const int passes = std::max(1, (bits + kRadixBits - 1) / kRadixBits);
+  const int ntiles = int((n + kRadixTile - 1) / kRadixTile);
+  const int64_t nh = int64_t(ntiles) * kRadixDigits;
+  int* hist = b.hist;
+  int* offs = b.hist + nh;
+  const int* kin = b.key_a;
+  const int* vin = nullptr;
+  for (int pass = 0; pass < passes; ++pass) {
+    const int shift = pass * kRadixBits;
+    const bool last = pass + 1 == passes;
+    int* kout = last ? nullptr : (kin == b.key_a ? b.key_b : b.key_a);
+    // the last pass writes perm; the ones before alternate so that it does
+    int* vout = ((passes - 1 - pass) % 2 == 0) ? b.perm : b.val_a;
+    hipLaunchKernelGGL(k_radix_hist, dim3(ntiles), dim3(kRadixThreads), 0, st, kin, n, shift,
+                       ntiles, hist);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_scan(hist, offs, nh, b.scan_tmp, b.scan_bytes, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_radix_scatter, dim3(ntiles), dim3(kRadixThreads), 0, st, kin, vin, n,
+                       shift, ntiles, offs, kout, vout);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    kin = kout;
+    vin = vout;
   }
+  if (fp64)
+    hipLaunchKernelGGL((k_gather_sorted<double4>), dim3(nb), dim3(256), 0, st,
+                       static_cast<const double4*>(b.stage4), b.perm, n, p.w,
+                       static_cast<double4*>(b.pos4), b.wsort);
+  else
+    hipLaunchKernelGGL((k_gather_sorted<float4>), dim3(nb), dim3(256), 0, st,
+                       static_cast<const float4*>(b.stage4), b.perm, n, p.w,
+                       static_cast<float4*>(b.pos4), b.wsort);
   return hipGetLastError();
 }
 

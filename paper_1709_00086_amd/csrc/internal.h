@@ -59,8 +59,14 @@ struct ConvTable {
   double tcoef[4096];
 };
 
-// Host: build the conversion table for a basis (0 cartesian, 1 spin).
+// Host: build the conversion table for a basis (0 cartesian, 1 spin with
+// powers u_z^n, 2 spin with Chebyshev polynomials T_n(u_z)).
 void build_conv_table(int basis, ConvTable* t);
+// The table a problem basis accumulates and converts with: the spin basis
+// sums (u_x - i u_y)^m T_n(u_z), so it converts with the spin-Chebyshev table.
+__host__ __device__ constexpr int conv_table_of(int basis) {
+  return basis == G3PCF_BASIS_SPIN ? int(G3PCF_BASIS_SPIN_T) : basis;
+}
 
 // Degenerate-triangle table G[m][l][l'][n]: Pbar_lm Pbar_l'm = sum_n G P_n.
 constexpr int kDegTable = (kDeg + 1) * (kDeg + 1) * (kDeg + 1) * kTermsDeg;
@@ -135,10 +141,24 @@ struct PairArgs {
 };
 
 // ---- launchers (each returns hipGetLastError after the launch) ----
-hipError_t launch_cells(const g3pcf_problem& p, const Grid& g, void* pos4, int* cell_start,
-                        int* cell_count, int* cid, int* perm, double* wsort, void* tmp4,
-                        int* tmp_perm, double* tmp_w, void* scan_tmp, size_t scan_tmp_bytes,
-                        int fp64, hipStream_t st);
+// Buffers of the cell-list stage (all device, n = galaxies).
+struct CellBufs {
+  void* pos4;          // [n] out: cell-order (x, y, z, w), float4 or double4
+  void* stage4;        // [n] scratch: the same values in input order
+  int* cell_start;     // [ncell + 1] out
+  int* cell_count;     // [ncell + 1] scratch
+  int* key_a;          // [n] scratch: cell ids (radix keys)
+  int* key_b;          // [n] scratch
+  int* val_a;          // [n] scratch: radix values
+  int* perm;           // [n] out: cell-order slot -> input index
+  int* hist;           // [2 radix_hist_ints(n)] scratch: digit counts and offsets
+  double* wsort;       // [n] out: FP64 weights in cell order
+  void* scan_tmp;      // scan scratch for max(ncell + 1, n + 1, radix_hist_ints(n)) entries
+  size_t scan_bytes;
+};
+size_t radix_hist_ints(int64_t n);
+hipError_t launch_cells(const g3pcf_problem& p, const Grid& g, const CellBufs& b, int fp64,
+                        hipStream_t st);
 // Primary list (cell order): galaxies in the mask (NULL: all) and, if region
 // is not NULL, with region[i] == r.
 hipError_t launch_primaries(const uint8_t* mask, const int32_t* region, int r, const int* perm,
@@ -177,8 +197,9 @@ struct ZetaArgs {
 // Every block of kZetaBlock primaries of a pair-block: z.sub_begin = 0 and
 // z.K = rows of the pair-block.
 hipError_t launch_zeta_pairblock(const ZetaArgs& z, hipStream_t st);
-// Doubles of the partial-Gram buffer (per-block partials of a pair-block).
-size_t zeta_partial_doubles(const RowLayout& L);
+// Doubles of the partial-Gram buffer (per-block partials of a pair-block of
+// at most PB primaries).
+size_t zeta_partial_doubles(const RowLayout& L, long long PB);
 
 // Adjoint helpers
 struct AdjArgs {

@@ -329,7 +329,26 @@ __host__ __device__ constexpr int spin_term_of(int m0, int m1, int i) {
   return -1;
 }
 
-// Spin chunk: S_{m,n} = sum w (u_x - i u_y)^m u_z^n for M0 <= m <= M1.
+// Chebyshev polynomials T_0..T_NMAX of z by their three-term recurrence
+// T_{n+1} = 2 z T_n - T_{n-1} (one FMA each).  In this basis the
+// coefficients of the spherical harmonics do not cancel: those of the powers
+// z^n do, by up to three orders of magnitude at l = 10 (for m = 0 they are
+// the power-basis coefficients of the Legendre polynomials), which costs
+// FP32 sums as many digits.
+template <int NMAX, typename Real>
+__device__ __forceinline__ void chebyshev(Real z, Real (&tn)[kDeg + 1]) {
+  tn[0] = Real(1);
+  tn[1] = z;
+  const Real z2 = z + z;
+  static_for<(NMAX > 1 ? NMAX - 1 : 0)>([&](auto nc) {
+    constexpr int n = decltype(nc)::value + 1;
+    tn[n + 1] = fma_r(z2, tn[n], -tn[n - 1]);
+  });
+}
+
+// Spin chunk: S_{m,n} = sum w (u_x - i u_y)^m T_n(u_z) for M0 <= m <= M1,
+// with T_n the Chebyshev polynomials (the conversion to a_lm uses the
+// spin-Chebyshev table).
 template <typename Real, int M0, int M1>
 struct SpinChunk {
   static constexpr int NT = spin_count(M0, M1);
@@ -344,9 +363,7 @@ struct SpinChunk {
   __device__ __forceinline__ void add(Real x, Real y, Real z, Real w) {
     constexpr int NMAX = kDeg - (M0 > 0 ? M0 : 0);
     Real zn[kDeg + 1];
-    zn[0] = Real(1);
-#pragma unroll
-    for (int n = 1; n <= NMAX; ++n) zn[n] = zn[n - 1] * z;
+    chebyshev<NMAX>(z, zn);
     if constexpr (M0 == 0) {
       acc[spin_local(M0, 0, 0, 0)] += w;
       static_for<kDeg>([&](auto nc) {
@@ -377,15 +394,13 @@ struct SpinChunk {
     }
   }
 
-  // adjoint: sum over this chunk of g_t * Re/Im parts of (x - i y)^m z^n,
-  // with the powers of z formed first so that every coefficient enters as a
+  // adjoint: sum over this chunk of g_t * Re/Im parts of (x - i y)^m T_n(z),
+  // with the T_n formed first so that every coefficient enters as a
   // multiplicand (a scalar-register operand when the coefficients are uniform).
   template <typename GetG>
   static __device__ __forceinline__ Real poly(Real x, Real y, Real z, GetG&& g) {
     Real zn[kDeg + 1];
-    zn[0] = Real(1);
-#pragma unroll
-    for (int n = 1; n <= kDeg; ++n) zn[n] = zn[n - 1] * z;
+    chebyshev<kDeg>(z, zn);
     Real total = Real(0);
     Real cr = Real(1), ci = Real(0);
     static_for<M1 + 1>([&](auto mc) {
@@ -459,11 +474,7 @@ struct SpinTPoly {
 
   __device__ __forceinline__ float eval(float x, float y, float z) const {
     float tn[kDeg + 1];
-    tn[0] = 1.0f;
-    tn[1] = z;
-    const float z2 = z + z;
-#pragma unroll
-    for (int n = 1; n < kDeg; ++n) tn[n + 1] = fma_r(z2, tn[n], -tn[n - 1]);
+    chebyshev<kDeg>(z, tn);
     float total = g[spin_index_c(0, 0, 0)];
     static_for<kDeg>([&](auto nc) {
       constexpr int n = decltype(nc)::value + 1;

@@ -264,7 +264,11 @@ constexpr int n_chunks(ChunkList<C...>) {
 }
 
 // ---------------------------------------------------------------- the kernel
-template <typename Real, int BASIS, bool ADJOINT>
+// kRot: line of sight towards the observer (every separation is rotated);
+// kMin: FP32 minimum image per candidate (a periodic axis where the search
+// window can wrap onto itself).  Both are fixed per launch, so each kernel
+// holds the code and the live values of one mode only.
+template <typename Real, int BASIS, bool ADJOINT, bool kRot, bool kMin>
 struct PairKernel {
   using V = typename V4<Real>::T;
   // FP32 adjoint: Chebyshev-basis polynomial in FP32 (SpinTPoly)
@@ -285,8 +289,7 @@ struct PairKernel {
     double prel[3];  // primary position in cell units, (p - lo) / s
     float sf[3];     // cell sides
     Real L[3], invL[3];
-    Real Rm[9];    // line-of-sight rotation
-    bool rotate;
+    Real Rm[9];    // line-of-sight rotation (kRot)
     bool minimg;   // minimum image per candidate (else the run's image shift)
     Bin64 bin64;
   };
@@ -847,9 +850,21 @@ struct PairKernel {
       P.p[0] = uniform_double(double(pv.x));
       P.p[1] = uniform_double(double(pv.y));
       P.p[2] = uniform_double(double(pv.z));
-      frame(a, P);
-      // uniform per primary: held in scalar registers
-      for (int i = 0; i < 9; ++i) P.Rm[i] = uniform_real(P.Rm[i]);
+      const long long row = qi;  // row of A within this pair-block
+      if (!(isfinite(P.p[0]) && isfinite(P.p[1]) && isfinite(P.p[2]))) {
+        // no separation from a non-finite position is accepted: no neighbours,
+        // a zero row of sums (forward), no secondary terms (adjoint)
+        if constexpr (!ADJOINT) {
+          double* out = a.A + row * a.lay.W;
+          for (int k = lane; k < a.lay.W; k += kWave) out[k] = 0.0;
+        }
+        continue;
+      }
+      if constexpr (kRot) {
+        frame(a, P);
+        // uniform per primary: held in scalar registers
+        for (int i = 0; i < 9; ++i) P.Rm[i] = uniform_real(P.Rm[i]);
+      }
       for (int c = 0; c < 3; ++c) {
         P.L[c] = uniform_real(Real(a.L[c]));
         P.invL[c] = uniform_real(Real(1.0 / a.L[c]));
@@ -860,14 +875,14 @@ struct PairKernel {
         P.bin64.L[c] = a.L[c];
       }
       // FP64 always measures from the primary with the minimum image (the
-      // plain definition); FP32 only where a search window can wrap onto itself
-      P.minimg = a.periodic && (!kF32 || a.tight[0] || a.tight[1] || a.tight[2]);
+      // plain definition); FP32 only where a search window can wrap onto
+      // itself (kMin)
+      P.minimg = kF32 ? kMin : (a.periodic != 0);
       P.bin64.minimg = P.minimg;
       P.bin64.r2max = a.rmax * a.rmax;
       P.bin64.nbins = nb;
       P.bin64.rmax = a.rmax;
 
-      const long long row = qi;  // row of A within this pair-block
       double w_prim = 0.0;
       if constexpr (ADJOINT) w_prim = a.wsort[slot];
 
@@ -876,30 +891,18 @@ struct PairKernel {
         const double r0 = uniform_double(fmax(0.0, b * a.rmax / nb - margin));
         const double r1 =
             uniform_double((b + 1 == nb) ? a.rmax_search : (b + 1) * a.rmax / nb + margin);
-        if (P.rotate) {
-          if (kF32 && P.minimg)
-            my_pairs += shell<true, kF32>(a, W, pos4, P, b, r0, r1, row, w_prim, sp);
-          else
-            my_pairs += shell<true, false>(a, W, pos4, P, b, r0, r1, row, w_prim, sp);
-        } else {
-          if (kF32 && P.minimg)
-            my_pairs += shell<false, kF32>(a, W, pos4, P, b, r0, r1, row, w_prim, sp);
-          else
-            my_pairs += shell<false, false>(a, W, pos4, P, b, r0, r1, row, w_prim, sp);
-        }
+        my_pairs += shell<kRot, kF32 && kMin>(a, W, pos4, P, b, r0, r1, row, w_prim, sp);
       }
     }
 
     if (lane == 0 && my_pairs) atomicAdd(a.pairs, my_pairs);
   }
 
-  // Line-of-sight frame of the primary: identity (z mode) or the Rodrigues
-  // rotation taking the direction from the observer to +z.
+  // Line-of-sight frame of the primary: the Rodrigues rotation taking the
+  // direction from the observer to +z (the identity for a primary on the
+  // observer, which has no line of sight).
   static __device__ __forceinline__ void frame(const PairArgs& a, Primary& P) {
     for (int i = 0; i < 9; ++i) P.Rm[i] = Real((i % 4 == 0) ? 1 : 0);
-    P.rotate = false;
-    if (a.los != G3PCF_LOS_OBSERVER) return;
-    P.rotate = true;
     const double* p = P.p;
     double n[3] = {p[0] - a.obs[0], p[1] - a.obs[1], p[2] - a.obs[2]};
     const double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
@@ -967,7 +970,7 @@ struct PairKernel {
   static __device__ __forceinline__ void convert(const PairArgs& a, const Lds& W, int b,
                                                  long long row) {
     const int lane = threadIdx.x % kWave;
-    const ConvTable& t = g_conv[BASIS];
+    const ConvTable& t = g_conv[conv_table_of(BASIS)];
     const RowLayout& L = a.lay;
     double* out = a.A + row * L.W;
     for (int o = lane; o < kOutPerBin; o += kWave) {
@@ -1016,26 +1019,45 @@ struct PairKernel {
   }
 };
 
-template <typename Real, int BASIS, bool ADJOINT>
+template <typename Real, int BASIS, bool ADJOINT, bool ROT, bool MIN>
 __global__ __launch_bounds__(kWave* kWavesPerBlock)
     __attribute__((amdgpu_waves_per_eu(Occ<Real, BASIS, ADJOINT>::value))) void k_pairs(
         PairArgs a) {
-  PairKernel<Real, BASIS, ADJOINT>::run(a);
+  PairKernel<Real, BASIS, ADJOINT, ROT, MIN>::run(a);
 }
 
 __global__ void k_zero_queue(int* q) {
   if (threadIdx.x < kQueues) q[threadIdx.x * kQueueStride] = 0;
 }
 
-template <typename Real, int BASIS, bool ADJOINT>
-hipError_t launch_one(const PairArgs& a, hipStream_t st) {
+template <typename Real, int BASIS, bool ADJOINT, bool ROT, bool MIN>
+hipError_t launch_mode(const PairArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(k_zero_queue, dim3(1), dim3(kWave), 0, st, a.queue);
   const long long want = (a.p_count + kWavesPerBlock - 1) / kWavesPerBlock;
   const unsigned blocks = unsigned(std::min<long long>(want, kPairWaves / kWavesPerBlock));
-  const size_t lds = sizeof(typename PairKernel<Real, BASIS, ADJOINT>::Lds) * kWavesPerBlock;
-  hipLaunchKernelGGL((k_pairs<Real, BASIS, ADJOINT>), dim3(blocks > 0 ? blocks : 1),
+  const size_t lds =
+      sizeof(typename PairKernel<Real, BASIS, ADJOINT, ROT, MIN>::Lds) * kWavesPerBlock;
+  hipLaunchKernelGGL((k_pairs<Real, BASIS, ADJOINT, ROT, MIN>), dim3(blocks > 0 ? blocks : 1),
                      dim3(kWave * kWavesPerBlock), lds, st, a);
   return hipGetLastError();
+}
+
+// The kernel of the problem's mode: rotation (observer line of sight) and,
+// for FP32, the minimum image (FP64 always applies it on a periodic box).
+template <typename Real, int BASIS, bool ADJOINT>
+hipError_t launch_one(const PairArgs& a, hipStream_t st) {
+  const bool rot = a.los == G3PCF_LOS_OBSERVER;
+  if constexpr (std::is_same<Real, float>::value) {
+    const bool mi = a.periodic && (a.tight[0] || a.tight[1] || a.tight[2]);
+    if (rot)
+      return mi ? launch_mode<Real, BASIS, ADJOINT, true, true>(a, st)
+                : launch_mode<Real, BASIS, ADJOINT, true, false>(a, st);
+    return mi ? launch_mode<Real, BASIS, ADJOINT, false, true>(a, st)
+              : launch_mode<Real, BASIS, ADJOINT, false, false>(a, st);
+  } else {
+    return rot ? launch_mode<Real, BASIS, ADJOINT, true, false>(a, st)
+               : launch_mode<Real, BASIS, ADJOINT, false, false>(a, st);
+  }
 }
 
 }  // namespace

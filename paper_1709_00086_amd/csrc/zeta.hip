@@ -444,9 +444,9 @@ RowLayout make_layout(int lmax, int nb) {
   return L;
 }
 
-size_t zeta_partial_doubles(const RowLayout& L) {
-  const int nsub_max = (kPairBlockMax + kZetaBlock - 1) / kZetaBlock;
-  return size_t(std::max(nsub_max, kZetaSplitK)) * size_t(sum_wm2(L));
+size_t zeta_partial_doubles(const RowLayout& L, long long PB) {
+  const long long nsub_max = (PB + kZetaBlock - 1) / kZetaBlock;
+  return size_t(std::max<long long>(nsub_max, kZetaSplitK)) * size_t(sum_wm2(L));
 }
 
 // All blocks of 4096 primaries of a pair-block (z.sub_begin = 0, z.K = rows).

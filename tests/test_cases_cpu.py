@@ -24,3 +24,18 @@ def test_32_shell_case_is_clear_of_shell_edges():
     cat = C.tiny(n=600, L=200.0, seed=19, rmax=60.0, nbins=32, lmax=10, periodic=True, los="z",
                  dtype=np.float32)
     assert _edge_margin(cat) > 9e-5
+
+
+def test_non_finite_case_is_clear_of_shell_edges():
+    # the GPU test of non-finite positions holds the FP32 gradient to 1e-4 of
+    # the oracle's: no finite pair of its catalogue may sit near a shell edge
+    for periodic in (True, False):
+        cat = C.tiny(n=400, L=100.0, seed=48, rmax=40.0, nbins=4, lmax=10, periodic=periodic,
+                     los="z")
+        assert _edge_margin(cat) > 1e-4
+
+
+def test_observer_case_is_clear_of_shell_edges():
+    cat = C.tiny(n=64, L=100.0, seed=13, rmax=50.0, nbins=3, lmax=8, periodic=False,
+                 los="observer")
+    assert _edge_margin(cat) > 1e-3
