@@ -23,7 +23,8 @@
  * Conventions shared by every entry point
  *   - Every pointer is a DEVICE pointer unless its comment says HOST.
  *   - The caller owns all memory.  The library keeps no allocation between
- *     calls; scratch lives in the caller's workspace `ws`.
+ *     calls; scratch lives in the caller's workspace `ws` (except for
+ *     g3pcf_forward_noalloc, whose scratch is a static device array).
  *   - Arguments are validated synchronously, before anything is enqueued; an
  *     invalid call returns a negative g3pcf_status and enqueues nothing.
  *   - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL is the
@@ -207,6 +208,24 @@ int g3pcf_alm_bytes(const g3pcf_problem* prob, size_t* bytes);
  * g3pcf_last_error).  On error the contents of zeta are unspecified. */
 int g3pcf_forward(const g3pcf_problem* prob, double* zeta, void* ws, size_t ws_bytes,
                   void* stream);
+
+/* Forward pass that allocates nothing, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Computes what g3pcf_forward computes for the same
+ * problem, with the scratch held in a static device array of the library
+ * (128 MiB per GPU, kept until the process ends) instead of a caller
+ * workspace: pair-blocks of 4096 primaries and no spill lists (a multi-chunk
+ * basis repeats its search per chunk).  The caller passes only the inputs and
+ * zeta (and, if set, the alm store).  Results equal g3pcf_forward's up to the
+ * order of the FP64 sums across blocks of primaries.
+ * Errors: as g3pcf_forward, and G3PCF_EINVAL when the problem needs more
+ * scratch than the array holds (at l_max = 10 and 10 shells, roughly above
+ * 1.2 million galaxies with FP32 pairs, 0.8 million with FP64 pairs, 0.35
+ * million with the BF16x3 zeta stage; the message states the size); nothing
+ * is enqueued then.  Every call on one GPU uses that
+ * GPU's one array: calls that overlap on one GPU (other streams, other host
+ * threads) race and must be ordered by the caller. */
+int g3pcf_forward_noalloc(const g3pcf_problem* prob, double* zeta, void* stream);
 
 /* Forward pass per region of primaries (the partial zeta of each region, e.g.
  * for jack-knife resampling: zeta without region r is the full zeta minus

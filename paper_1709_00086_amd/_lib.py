@@ -21,7 +21,8 @@ EXPORTED = ["g3pcf_zeta_len", "g3pcf_num_terms", "g3pcf_workspace_bytes", "g3pcf
             "g3pcf_backward", "g3pcf_last_error", "g3pcf_conj_ylm_via_monomials",
             "g3pcf_trace_create", "g3pcf_trace_reset", "g3pcf_trace_read",
             "g3pcf_trace_destroy", "g3pcf_isotropic", "g3pcf_degenerate_term",
-            "g3pcf_forward_regions", "g3pcf_alm_bytes", "g3pcf_forward_batch"]
+            "g3pcf_forward_regions", "g3pcf_alm_bytes", "g3pcf_forward_batch",
+            "g3pcf_forward_noalloc"]
 STAGES = {0: "cells", 1: "pairs", 2: "zeta", 3: "adj_coef", 4: "pair_adjoint", 5: "distinct"}
 
 
@@ -87,6 +88,8 @@ def load():
     lib.g3pcf_forward.argtypes = [P, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                   ctypes.c_void_p]
     lib.g3pcf_forward.restype = ctypes.c_int
+    lib.g3pcf_forward_noalloc.argtypes = [P, ctypes.c_void_p, ctypes.c_void_p]
+    lib.g3pcf_forward_noalloc.restype = ctypes.c_int
     lib.g3pcf_backward.argtypes = [P, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_size_t, ctypes.c_void_p]
     lib.g3pcf_backward.restype = ctypes.c_int
@@ -149,6 +152,12 @@ def forward(prob: Problem, zeta_ptr: int, ws_ptr: int, ws_bytes: int, stream: in
     check(load().g3pcf_forward(ctypes.byref(prob), ctypes.c_void_p(zeta_ptr),
                                ctypes.c_void_p(ws_ptr), ctypes.c_size_t(ws_bytes),
                                ctypes.c_void_p(stream)))
+
+
+def forward_noalloc(prob: Problem, zeta_ptr: int, stream: int):
+    """g3pcf_forward_noalloc: the forward pass in the library's static scratch."""
+    check(load().g3pcf_forward_noalloc(ctypes.byref(prob), ctypes.c_void_p(zeta_ptr),
+                                       ctypes.c_void_p(stream)))
 
 
 def backward(prob: Problem, gz_ptr: int, gw_ptr: int, ws_ptr: int, ws_bytes: int, stream: int):

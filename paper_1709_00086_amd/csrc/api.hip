@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <set>
 #include <string>
@@ -460,6 +461,36 @@ int forward_run(const g3pcf_problem& p, const Ws& w, double* zeta, void* ws, hip
 }
 
 
+// Scratch of the allocation-free entry point g3pcf_forward_noalloc: one
+// array per device, held until the process ends.  In host code the array's
+// name is a stand-in only; its device address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+constexpr size_t kScratchBytes = size_t(128) << 20;
+// Primaries per pair-block in the scratch (one zeta block of 4096 rows).
+constexpr int64_t kScratchPairBlock = kZetaBlock;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;
+
+int scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it == g_scratch_ptr.end()) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr || reinterpret_cast<uintptr_t>(ptr) % kAlign)
+      return fail(G3PCF_EHIP, "scratch array has no usable device address");
+    it = g_scratch_ptr.emplace(dev, ptr).first;
+  }
+  *out = it->second;
+  return G3PCF_OK;
+}
+
 }  // namespace
 }  // namespace g3
 
@@ -554,6 +585,22 @@ int g3pcf_forward(const g3pcf_problem* prob, double* zeta, void* ws, size_t ws_b
   if ((rc = check_workspace(w, ws, ws_bytes))) return rc;
   return forward_run(*prob, w, zeta, ws, static_cast<hipStream_t>(stream));
 }
+
+int g3pcf_forward_noalloc(const g3pcf_problem* prob, double* zeta, void* stream) {
+  int rc = validate(prob);
+  if (rc) return rc;
+  if (!zeta) return fail(G3PCF_EINVAL, "zeta is NULL");
+  const Ws w = plan(*prob, 0, kScratchPairBlock, false);
+  if (w.total > kScratchBytes)
+    return fail(G3PCF_EINVAL, "g3pcf_forward_noalloc: this problem needs " +
+                                  std::to_string(w.total) + " bytes of scratch, the library "
+                                  "holds " + std::to_string(kScratchBytes) +
+                                  " (use g3pcf_forward with a workspace)");
+  void* ws = nullptr;
+  if ((rc = scratch_address(&ws))) return rc;
+  return forward_run(*prob, w, zeta, ws, static_cast<hipStream_t>(stream));
+}
+
 
 int g3pcf_forward_regions(const g3pcf_problem* prob, const int32_t* region, int nregions,
                           double* zeta, void* ws, size_t ws_bytes, void* stream) {
