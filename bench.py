@@ -146,13 +146,13 @@ def summarise_rocprof(args):
            "launches_counted": {k: len(v) for k, v in sorted(per.items())},
            "commands": args.commands or []}
     if args.copy_mib and "FETCH_SIZE" in copy and "WRITE_SIZE" in copy:
+        # the calibration copy is the largest copy dispatch of each run (the
+        # runs also copy a few bytes back to the host)
         kib = args.copy_mib * 1024.0
-        fs = kib / statistics.fmean(copy["FETCH_SIZE"])
-        wsc = kib / statistics.fmean(copy["WRITE_SIZE"])
-        rec.update({"copy_reference_mib": args.copy_mib,
-                    "copy_fetch_kib_raw": statistics.fmean(copy["FETCH_SIZE"]),
-                    "copy_write_kib_raw": statistics.fmean(copy["WRITE_SIZE"]),
-                    "fetch_scale": fs, "write_scale": wsc})
+        cf, cw = max(copy["FETCH_SIZE"]), max(copy["WRITE_SIZE"])
+        fs, wsc = kib / cf, kib / cw
+        rec.update({"copy_reference_mib": args.copy_mib, "copy_fetch_kib_raw": cf,
+                    "copy_write_kib_raw": cw, "fetch_scale": fs, "write_scale": wsc})
         if "FETCH_SIZE" in per and "WRITE_SIZE" in per:
             f = statistics.fmean(per["FETCH_SIZE"])
             w = statistics.fmean(per["WRITE_SIZE"])
@@ -166,17 +166,123 @@ def summarise_rocprof(args):
             fl += 64.0 * mult * c[k]
     if fl:
         rec["valu_f32_flops_per_launch"] = fl
-    if args.kernel_stats:
-        for path in _find([args.kernel_stats], "kernel_stats.csv"):
-            for r in _csv_rows(path):
-                if pat.search(r.get("Name", "")):
-                    rec["trace_avg_ms"] = float(r["AverageNs"]) * 1e-6
-                    rec["trace_calls"] = int(r["Calls"])
+    # matrix-core work: each MOPS count is 512 flops
+    mf = {k: 512.0 * v for k, v in c.items() if k.startswith("SQ_INSTS_VALU_MFMA_MOPS_")}
+    if mf:
+        rec["mfma_flops_per_launch"] = mf
+    for path in _find(args.kernel_stats, "kernel_stats.csv"):
+        for r in _csv_rows(path):
+            if pat.search(r.get("Name", "")):
+                rec["trace_avg_ms"] = float(r["AverageNs"]) * 1e-6
+                rec["trace_calls"] = int(r["Calls"])
+    if "trace_avg_ms" not in rec:  # a --kernel-trace run without --stats
+        durs = [float(r["End_Timestamp"]) - float(r["Start_Timestamp"])
+                for path in _find(args.kernel_stats, "kernel_trace.csv")
+                for r in _csv_rows(path) if pat.search(r.get("Kernel_Name", ""))]
+        if durs:
+            rec["trace_avg_ms"] = statistics.fmean(durs) * 1e-6
+            rec["trace_calls"] = len(durs)
+    if mf and "trace_avg_ms" in rec:
+        peaks = {"F32": PEAK["fp32_mfma_tflops"], "F64": PEAK["fp64_mfma_tflops"],
+                 "BF16": PEAK["bf16_mfma_tflops"]}
+        rec["mfma_tflops"] = {k: v / (rec["trace_avg_ms"] * 1e-3) / 1e12 for k, v in mf.items()}
+        rec["mfma_frac_of_peak"] = {
+            k: v / peaks[k.rsplit("_", 1)[1]] for k, v in rec["mfma_tflops"].items()
+            if k.rsplit("_", 1)[1] in peaks and v > 0}
     if args.out:
         with open(args.out, "w") as f:
             json.dump(rec, f, indent=1)
             f.write("\n")
     print(json.dumps(rec, indent=1))
+
+
+# ---------------------------------------------------------------- precision report
+def _errors(z, ref, floor=1e-6):
+    """Per m and per (l, l'): the normwise error max|dz| / max|ref| and the
+    largest per-entry relative error over entries with |ref| >= floor max|ref|."""
+    L1 = z.shape[0]
+    scale = np.abs(ref).max()
+    d = np.abs(z - ref)
+    big = np.abs(ref) >= floor * scale
+    rel = np.where(big, d / np.where(big, np.abs(ref), 1.0), 0.0)
+    per_m = [(float(d[m].max() / scale), float(rel[m].max())) for m in range(L1)]
+    per_ll = [[float(rel[:, l, lp].max()) for lp in range(L1)] for l in range(L1)]
+    return {"norm": float(d.max() / scale), "per_entry": float(rel.max()), "per_m": per_m,
+            "per_ll": per_ll}
+
+
+def precision_report():
+    """Errors of the zeta stage on its own (the same FP64 pair stage feeding
+    FP64, FP32 and BF16x3 Gram products) and of the FP32 pair path, against
+    the FP64 oracle: config1 (one block of 4096 primaries) and the config2
+    catalogue with 65,536 seeded primaries (16 blocks, so the FP64 sum across
+    blocks is exercised).  Prints JSON and markdown tables."""
+    import torch
+    import oracle
+    from paper_1709_00086_amd import api, catalogues as C
+    dev = torch.device("cuda:0")
+    report = {}
+    for label, cat, mask_np in (
+            ("config1", C.config1(), None),
+            ("config2_16_blocks", C.config2(), C.primary_mask(1 << 20, 65536, seed=9))):
+        t = time.perf_counter()
+        ref = oracle.zeta(cat, primary_mask=mask_np)
+        log(f"{label}: oracle {time.perf_counter() - t:.1f} s")
+        pos = torch.from_numpy(cat.pos).to(dev)
+        w = torch.from_numpy(cat.w).to(dev)
+        m = torch.from_numpy(mask_np).to(dev) if mask_np is not None else None
+
+        def run(prec, zp=None):
+            cfg = api.Config(box=cat.box, rmax=cat.rmax, nbins=cat.nbins, lmax=cat.lmax,
+                             los=cat.los, observer=cat.observer, periodic=cat.periodic,
+                             box_lo=cat.box_lo, precision=prec, basis="spin", zeta_precision=zp)
+            return api.zeta(pos, w, cfg, primary_mask=m).cpu().numpy()
+        rows = {}
+        z64 = run("fp64", "fp64")
+        rows["FP64 pairs, FP64 zeta stage"] = _errors(z64, ref)
+        for zp in ("fp32", "bf16x3"):
+            rows[f"FP64 pairs, {zp.upper()} zeta stage"] = _errors(run("fp64", zp), ref)
+        for zp in ("fp32", "bf16x3"):
+            rows[f"FP32 pairs, {zp.upper()} zeta stage"] = _errors(run("fp32", zp), ref)
+        report[label] = rows
+    print(json.dumps(report))
+    for label, rows in report.items():
+        print(f"\n### {label}: normwise error max|dz|/max|z| and largest per-entry relative "
+              f"error (entries with |z| >= 1e-6 max|z|)\n")
+        print("| path | all | " + " | ".join(f"m={m}" for m in range(11)) + " |")
+        print("|---|---|" + "---|" * 11)
+        for name, e in rows.items():
+            cells = " | ".join(f"{a:.1e} / {b:.1e}" for a, b in e["per_m"])
+            print(f"| {name} | {e['norm']:.1e} / {e['per_entry']:.1e} | {cells} |")
+        for name in ("FP32 pairs, FP32 zeta stage", "FP32 pairs, BF16X3 zeta stage"):
+            e = rows[name]
+            print(f"\n{label}, {name}: largest per-entry relative error per (l, l') "
+                  f"(rows l, columns l')\n")
+            print("| l \\ l' | " + " | ".join(str(l) for l in range(11)) + " |")
+            print("|---|" + "---|" * 11)
+            for l in range(11):
+                print(f"| {l} | " + " | ".join(f"{v:.0e}" for v in e["per_ll"][l]) + " |")
+
+
+# ---------------------------------------------------------------- probes
+PROBE_SRC = os.path.join(ROOT, "bench_probes.hip")
+PROBE_BIN = os.path.join(ROOT, "paper_1709_00086_amd", "_build", "bench_probes")
+
+
+def probes(args):
+    """Build (on any machine with hipcc) or run (on the GPU) bench_probes.hip."""
+    import subprocess
+    if args.build_probes:
+        os.makedirs(os.path.dirname(PROBE_BIN), exist_ok=True)
+        subprocess.check_call(["hipcc", "-O3", "-std=c++17", "--offload-arch=gfx950", "-Xclang",
+                               "-target-feature", "-Xclang", "-packed-fp32-ops",
+                               "-Wno-unused-command-line-argument", "-I", ROOT, PROBE_SRC,
+                               "-o", PROBE_BIN])
+        log(f"built {PROBE_BIN}")
+    if args.probes:
+        if not os.path.exists(PROBE_BIN):
+            raise SystemExit(f"{PROBE_BIN} is missing: python bench.py --build-probes")
+        sys.exit(subprocess.call([PROBE_BIN, args.probes]))
 
 
 # ---------------------------------------------------------------- timing helpers
@@ -245,11 +351,19 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--precision-report", action="store_true",
+                    help="per-(m, l, l') errors of the FP32 and BF16x3 zeta stages and of the "
+                         "FP32 path against the FP64 oracle (config1 and a 16-block 2^20 "
+                         "sample); prints a markdown report")
+    ap.add_argument("--build-probes", action="store_true",
+                    help="compile bench_probes.hip (issue-rate and counter-calibration probes)")
+    ap.add_argument("--probes", default=None, metavar="MODE",
+                    help="run the built probes: fma, accum, count or all (GPU)")
     ap.add_argument("--summarise-rocprof", action="store_true",
                     help="summarise rocprofv3 CSV output instead of running (no GPU)")
     ap.add_argument("--counters", nargs="*", default=[])
-    ap.add_argument("--kernel-stats", default=None)
-    ap.add_argument("--kernel-regex", default=r"k_pairs<float, 1, false>")
+    ap.add_argument("--kernel-stats", nargs="*", default=[])
+    ap.add_argument("--kernel-regex", default=r"k_pairs<float, 1, false, false, false>")
     ap.add_argument("--label", default=None)
     ap.add_argument("--copy-mib", type=int, default=0)
     ap.add_argument("--commands", nargs="*", default=None)
@@ -257,6 +371,12 @@ def main():
     args = ap.parse_args()
     if args.summarise_rocprof:
         summarise_rocprof(args)
+        return
+    if args.precision_report:
+        precision_report()
+        return
+    if args.build_probes or args.probes:
+        probes(args)
         return
     if args.distinct or args.regions or args.batch:
         args.forward_only = True

@@ -103,7 +103,7 @@ typedef enum {
 typedef struct g3pcf_trace g3pcf_trace;
 
 typedef struct {
-  int64_t n;               /* number of galaxies, 0 <= n < 2^31                  */
+  int64_t n;               /* number of galaxies, 0 <= n < 2^27                  */
   const void* pos;         /* [n][3] row-major positions, dtype pos_dtype         */
   g3pcf_dtype pos_dtype;
   const double* w;         /* [n] weights                                         */

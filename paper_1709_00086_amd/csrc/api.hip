@@ -141,8 +141,10 @@ bool finite3(const double* v) {
 
 int validate(const g3pcf_problem* p) {
   if (!p) return fail(G3PCF_EINVAL, "problem is NULL");
-  if (p->n < 0 || p->n >= (int64_t(1) << 31) - 64)
-    return fail(G3PCF_EINVAL, "n must satisfy 0 <= n < 2^31 - 64");
+  // the pair kernels address the cell-ordered catalogue (16 or 32 bytes per
+  // galaxy) with 32-bit byte offsets
+  if (p->n < 0 || p->n >= (int64_t(1) << 27))
+    return fail(G3PCF_EINVAL, "n must satisfy 0 <= n < 2^27");
   if (p->n > 0 && (!p->pos || !p->w)) return fail(G3PCF_EINVAL, "pos and w must be non-NULL");
   if (p->pos_dtype != G3PCF_F32 && p->pos_dtype != G3PCF_F64)
     return fail(G3PCF_EINVAL, "pos_dtype must be G3PCF_F32 or G3PCF_F64");

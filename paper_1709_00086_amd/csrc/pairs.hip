@@ -463,6 +463,13 @@ struct PairKernel {
     return e.g0 + vc;
   }
 
+  // Galaxy j of the cell-ordered catalogue through a 32-bit byte offset from
+  // the scalar base address (the catalogue is below 4 GiB: n < 2^27).
+  static __device__ __forceinline__ V load_galaxy(const V* __restrict__ pos4, int j) {
+    return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(pos4) +
+                                       (unsigned(j) * unsigned(sizeof(V))));
+  }
+
   // Unit separation (rotated into the line-of-sight frame) of a ring entry.
   template <bool ROT>
   static __device__ __forceinline__ void unit(const Primary& P, const V& e, Real& ux, Real& uy,
@@ -539,6 +546,7 @@ struct PairKernel {
         const bool valid = v0 + lane < total;
         Real d[3];
         bool acc;
+        unsigned long long m;
         if constexpr (kF32) {
           const float* ref = MINIMG ? P.pref : rref;
           float dx = __fsub_rn(q.x, ref[0]), dy = __fsub_rn(q.y, ref[1]),
@@ -553,12 +561,13 @@ struct PairKernel {
           d[1] = dy;
           d[2] = dz;
           acc = valid & (r2 > lo2) & (r2 < hi2);  // no short circuit: no branches
+          m = ballot(acc);
         } else {
           double r2;
           const int bin = P.bin64.classify(q, P.p, d, r2);
           acc = valid && bin == b;
+          m = ballot(acc);
         }
-        const unsigned long long m = ballot(acc);
         if (acc) {
           V ent;
           ent.x = d[0];
@@ -592,13 +601,13 @@ struct PairKernel {
       Real refa[3] = {P.pref[0], P.pref[1], P.pref[2]};
       Real refb[3] = {P.pref[0], P.pref[1], P.pref[2]};
       int ja = map_window(W, nrun, total, 0, kb, kbase, prec, refa);
-      V qa = pos4[ja];
+      V qa = load_galaxy(pos4, ja);
       for (int v0 = 0; v0 < total; v0 += 2 * kWave) {
         const int jb = map_window(W, nrun, total, v0 + kWave, kb, kbase, prec, refb);
-        const V qb = pos4[jb];
+        const V qb = load_galaxy(pos4, jb);
         step(qa, refa, ja, v0);
         ja = map_window(W, nrun, total, v0 + 2 * kWave, kb, kbase, prec, refa);
-        qa = pos4[ja];
+        qa = load_galaxy(pos4, ja);
         step(qb, refb, jb, v0 + kWave);
       }
       wave_lds_fence();
@@ -680,13 +689,13 @@ struct PairKernel {
     };
     int ja = sp[min(lane, last)];
     int jb = sp[min(kWave + lane, last)];
-    V qa = pos4[ja];
+    V qa = load_galaxy(pos4, ja);
     for (int base = 0; base < count; base += 2 * kWave) {
-      const V qb = pos4[jb];
+      const V qb = load_galaxy(pos4, jb);
       const int jn = sp[min(base + 2 * kWave + lane, last)];
       use(qa, ja, base);
       ja = jn;
-      qa = pos4[ja];
+      qa = load_galaxy(pos4, ja);
       const int jbb = jb;
       jb = sp[min(base + 3 * kWave + lane, last)];
       use(qb, jbb, base + kWave);

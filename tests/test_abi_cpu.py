@@ -113,6 +113,7 @@ def _problem(**kw):
     dict(nbins=0),
     dict(nbins=33),
     dict(n=-5),
+    dict(n=1 << 27),                  # the catalogue is addressed with 32-bit offsets
     dict(pos=None),
     dict(pos_dtype=7),
     dict(box=(100.0, 0.0, 100.0)),
@@ -186,6 +187,23 @@ def test_degenerate_term_reproduces_scipy_ylm_products(lib):
         for m in range(lmax + 1):
             ref[m] = (np.conj(Y[:, m])[:, None] * Y[:, m][None, :]).real
         assert np.abs(got - ref).max() <= 1e-12
+
+
+@pytest.mark.skipif(os.path.exists("/dev/kfd"), reason="a GPU driver is present")
+def test_valid_call_without_a_device_returns_ehip(lib):
+    """With no GPU, valid calls fail with G3PCF_EHIP and the HIP error text
+    (the first device call is the table upload or the scratch address)."""
+    p = _problem(n=0)
+    need = _lib.workspace_bytes(p, 0)
+    rc = lib.g3pcf_forward(ctypes.byref(p), ctypes.c_void_p(0x3000), ctypes.c_void_p(0x100000),
+                           need, None)
+    assert rc == _lib.EHIP
+    assert len(lib.g3pcf_last_error()) > 0
+    rc = lib.g3pcf_forward_noalloc(ctypes.byref(_problem()), ctypes.c_void_p(0x3000), None)
+    assert rc == _lib.EHIP
+    rc = lib.g3pcf_backward(ctypes.byref(p), ctypes.c_void_p(0x3000), ctypes.c_void_p(0x4000),
+                            ctypes.c_void_p(0x100000), _lib.workspace_bytes(p, 1), None)
+    assert rc == _lib.EHIP
 
 
 def test_distinct_backward_is_unsupported_before_device_work(lib):
