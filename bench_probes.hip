@@ -144,12 +144,12 @@ int main(int argc, char** argv) {
     for (int w : {3, 4}) accum_rate<SpinChunk<float, 0, kDeg>>(out, "spin", w, 164);
   }
   if (all || !std::strcmp(mode, "count")) {
-    // 1024 waves x (4 iterations x 256 FMAs in the loop + 17 outside it: the
-    // 16 initial values and the per-lane multiplicand, as compiled)
+    // 1024 waves x (4 iterations x 256 FMAs in the loop + 18 outside it: the
+    // 16 initial values and the two per-lane operands, as compiled)
     hipLaunchKernelGGL((k_fma<16, false>), dim3(256), dim3(256), 0, 0, out, 4, 0.999f, 1e-3f);
     if (check(hipDeviceSynchronize(), "count launch"))
       std::printf("{\"probe\": \"count\", \"expected_wave_fma_f32\": %d}\n",
-                  256 * 4 * (4 * 256 + 17));
+                  256 * 4 * (4 * 256 + 18));
   }
   (void)hipFree(out);
   return 0;

@@ -220,8 +220,8 @@ int g3pcf_forward(const g3pcf_problem* prob, double* zeta, void* ws, size_t ws_b
  * order of the FP64 sums across blocks of primaries.
  * Errors: as g3pcf_forward, and G3PCF_EINVAL when the problem needs more
  * scratch than the array holds (at l_max = 10 and 10 shells, roughly above
- * 1.2 million galaxies with FP32 pairs, 0.8 million with FP64 pairs, 0.35
- * million with the BF16x3 zeta stage; the message states the size); nothing
+ * 1.2 million galaxies with FP32 pairs, with either FP32 zeta stage, and 0.8
+ * million with FP64 pairs; the message states the size); nothing
  * is enqueued then.  Every call on one GPU uses that
  * GPU's one array: calls that overlap on one GPU (other streams, other host
  * threads) race and must be ordered by the caller. */

@@ -63,11 +63,10 @@ size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Ws {
   size_t pos4, tmp4, cid, perm, tmp_perm, rkey, rhist, wsort, cell_start, cell_count, flags,
-      plist, scan, counters, spill, A, C, ops, gcoef, gsort, gsort32, mht, hrows, degD, degP;
+      plist, scan, counters, spill, A, C, gcoef, gsort, gsort32, mht, hrows, degD, degP;
   size_t scan_bytes;
   size_t total;
   int64_t PB;   // primaries per pair-block
-  int Kp;       // padded rows of a zeta sub-block (bf16 operands)
   int spill_cap;  // spill-list entries per wave (0: none)
   Grid grid;
   RowLayout lay;
@@ -86,7 +85,6 @@ Ws plan(const g3pcf_problem& p, int backward, int64_t pb_max = kPairBlockMax,
   w.lay = make_layout(p.lmax, p.nbins);
   const int64_t ncell = w.grid.ncell;
   w.PB = std::max<int64_t>(1, std::min<int64_t>(n, pb_max));
-  w.Kp = ((std::min<int64_t>(kZetaBlock, w.PB) + 31) / 32) * 32;
   const int64_t nhist = int64_t(radix_hist_ints(n));
   w.scan_bytes = scan_tmp_bytes(std::max<int64_t>(std::max<int64_t>(ncell + 1, n + 1), nhist));
   size_t at = 0;
@@ -115,8 +113,6 @@ Ws plan(const g3pcf_problem& p, int backward, int64_t pb_max = kPairBlockMax,
   w.spill_cap = multi ? kSpillCap : 0;
   w.A = take(size_t(w.PB) * w.lay.W * 8);
   w.C = take(zeta_partial_doubles(w.lay, w.PB) * 8);
-  w.ops = (!backward && p.zeta_prec == G3PCF_PREC_BF16X3) ? take(size_t(6) * w.lay.W * w.Kp * 2)
-                                                           : take(0);
   // degenerate triangles: per-shell Legendre sums and their per-workgroup partials
   const bool deg = !backward && p.distinct;
   w.degD = take(deg ? size_t(p.nbins) * (2 * p.lmax + 1) * 8 : 0);
@@ -393,8 +389,6 @@ int forward_pairs(const g3pcf_problem& p, const Ws& w, void* ws, double* zeta, i
       z.sub_begin = 0;
       z.K = a.p_count;
       z.lay = w.lay;
-      z.ops = at<void>(ws, w.ops);
-      z.C32 = at<float>(ws, w.C);
       z.C64 = at<double>(ws, w.C);
       z.zeta = zeta;
       z.prec = p.zeta_prec;

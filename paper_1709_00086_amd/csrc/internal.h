@@ -188,9 +188,7 @@ struct ZetaArgs {
   long long sub_begin;       // first row of this sub-block (relative to A)
   long long K;               // rows in this sub-block (upper bound)
   RowLayout lay;
-  void* ops;                 // bf16 split operands
-  float* C32;                // partial Gram products (FP32 / BF16X3)
-  double* C64;               // partial Gram products (FP64)
+  double* C64;               // per-block partial Gram products (FP64)
   double* zeta;
   int prec;
 };

@@ -24,47 +24,6 @@ typedef float float4_t __attribute__((ext_vector_type(4)));
 typedef double double4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 
-constexpr int kTile = 16;
-
-struct Dims {
-  int nm;                 // lmax + 1
-  int W[kDeg + 1];        // block widths
-  int off[kDeg + 1];      // column offsets in an A row
-  int cw[kDeg + 2];       // offsets of each C_m in the partial buffer
-  int tiles[kDeg + 2];    // cumulative tile counts
-  int rowW;               // A row width
-  int csize;              // sum W_m^2
-};
-
-Dims make_dims(const RowLayout& L) {
-  Dims d{};
-  d.nm = L.lmax + 1;
-  d.rowW = L.W;
-  int cw = 0, tiles = 0;
-  for (int m = 0; m < d.nm; ++m) {
-    d.W[m] = L.wm[m];
-    d.off[m] = L.off[m];
-    d.cw[m] = cw;
-    d.tiles[m] = tiles;
-    cw += L.wm[m] * L.wm[m];
-    const int t = (L.wm[m] + kTile - 1) / kTile;
-    tiles += t * t;
-  }
-  d.cw[d.nm] = cw;
-  d.tiles[d.nm] = tiles;
-  d.csize = cw;
-  return d;
-}
-
-__device__ __forceinline__ void tile_of(const Dims& d, int t, int& m, int& ti, int& tj) {
-  m = 0;
-  while (m + 1 < d.nm && t >= d.tiles[m + 1]) ++m;
-  const int r = t - d.tiles[m];
-  const int nt = (d.W[m] + kTile - 1) / kTile;
-  ti = r / nt;
-  tj = r % nt;
-}
-
 __device__ __forceinline__ long long valid_rows(const ZetaArgs& z) {
   // primaries in the pair-block, then rows of this sub-block
   const long long in_block = (long long)(*z.nprim) - z.row_begin;
@@ -262,6 +221,152 @@ __global__ __launch_bounds__(256) void k_gram_mt(ZetaArgs z, MDims d, double* __
       }
 }
 
+// ---- BF16x3: the same macro tiles and blocks as k_gram_mt, with every FP32
+// operand x split as x0 + x1 + x2, each xk the round-to-nearest-even bfloat16
+// of what is left, and the six products with i + j <= 2 on the bfloat16
+// matrix cores (FP32 accumulation over kFlush rows, then FP64).  Wave w stages
+// rows 8w..8w+7 of each 32-row step, one column per lane: the eight values of
+// a column are split and written to LDS as one 16-byte vector per part, laid
+// out [column][row] so that an MFMA lane reads its eight rows of a column with
+// one load.  The rows' weights come from lanes 0..31 of each wave by readlane.
+constexpr int kBPad = 8;  // bf16 padding of a column's 32 rows (bank spread)
+
+__global__ __launch_bounds__(256) void k_gram_bf16x3_mt(ZetaArgs z, MDims d,
+                                                        double* __restrict__ Cpart) {
+  __shared__ bf16x8_t Xs[2][3][kMT][(kKS + kBPad) / 8];
+  __shared__ bf16x8_t Ys[2][3][kMT][(kKS + kBPad) / 8];
+  const int tid = threadIdx.x;
+  const int lane = tid % kWave;
+  const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
+  const int s = blockIdx.y;
+  int m, ti, tj;
+  macro_tile_of(d, blockIdx.x, m, ti, tj);
+  const int W = d.W[m];
+  const bool diag = (ti == tj);
+  const long long Kv = valid_rows(z);
+  const long long r0 = (long long)s * kZetaBlock;
+  const long long r1 = min(Kv, r0 + kZetaBlock);
+  const double* A = z.A + d.off[m];
+  const int* plist = z.plist + z.row_begin;
+  const int ci = ti * kMT + lane, cj = tj * kMT + lane;
+
+  double xr[8], yr[8], wgt[8];
+  auto load = [&](long long kb) {
+    // lanes 0..31 fetch the step's weights; every lane takes its wave's 8
+    const long long rw = kb + lane;
+    const double wl = (lane < kKS && rw < r1) ? z.wsort[plist[rw]] : 0.0;
+    const long long wb = __double_as_longlong(wl);
+    const int wlo = int(wb & 0xffffffffll), whi = int(wb >> 32);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int lo = __builtin_amdgcn_readlane(wlo, 8 * wv + q);
+      const int hi = __builtin_amdgcn_readlane(whi, 8 * wv + q);
+      wgt[q] = __longlong_as_double((static_cast<long long>(hi) << 32) |
+                                    static_cast<unsigned int>(lo));
+      const long long r = kb + 8 * wv + q;
+      const bool ok = r < r1;
+      const double* row = A + (ok ? r : r0) * (long long)z.lay.W;
+      xr[q] = (ok && ci < W) ? row[ci] : 0.0;
+      if (!diag) yr[q] = (ok && cj < W) ? row[cj] : 0.0;
+    }
+  };
+  auto split8 = [](const float v[8], bf16x8_t parts[3]) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      float rem = v[q];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const __bf16 h = static_cast<__bf16>(rem);
+        parts[k][q] = h;
+        rem -= float(h);
+      }
+    }
+  };
+  auto store = [&](int buf) {
+    float xv[8], yv[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      xv[q] = float(wgt[q] * xr[q]);
+      yv[q] = float(diag ? xr[q] : yr[q]);
+    }
+    bf16x8_t xp[3], yp[3];
+    split8(xv, xp);
+    split8(yv, yp);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      Xs[buf][k][lane][wv] = xp[k];
+      Ys[buf][k][lane][wv] = yp[k];
+    }
+  };
+
+  float4_t acc[2][2];
+  double4_t tot[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      acc[a][b] = float4_t{0.f, 0.f, 0.f, 0.f};
+      tot[a][b] = double4_t{0.0, 0.0, 0.0, 0.0};
+    }
+  auto flush = [&]() {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          tot[a][b][r] += double(acc[a][b][r]);
+          acc[a][b][r] = 0.f;
+        }
+  };
+  const int qi = (wv >> 1) * 32, qj = (wv & 1) * 32;
+  const int li = lane % 16, g = lane / 16;
+
+  int buf = 0;
+  if (r0 < r1) {
+    load(r0);
+    store(0);
+  }
+  __syncthreads();
+  for (long long kb = r0; kb < r1; kb += kKS) {
+    const bool more = kb + kKS < r1;
+    if (kb > r0 && (kb - r0) % kFlush == 0) flush();
+    if (more) load(kb + kKS);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const bf16x8_t x0 = Xs[buf][0][qi + a * 16 + li][g], x1 = Xs[buf][1][qi + a * 16 + li][g],
+                       x2 = Xs[buf][2][qi + a * 16 + li][g];
+        const bf16x8_t y0 = Ys[buf][0][qj + b * 16 + li][g], y1 = Ys[buf][1][qj + b * 16 + li][g],
+                       y2 = Ys[buf][2][qj + b * 16 + li][g];
+        float4_t c = acc[a][b];
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x2, y0, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1, y1, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0, y2, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1, y0, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0, y1, c, 0, 0, 0);
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0, y0, c, 0, 0, 0);
+      }
+    if (more) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+
+  flush();
+  double* C = Cpart + (long long)s * d.csize + d.cw[m];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = ti * kMT + qi + a * 16 + 4 * g + r;
+        const int j = tj * kMT + qj + b * 16 + li;
+        if (i < W && j < W) C[i * W + j] = tot[a][b][r];
+      }
+}
+
 // zeta[m][l][l'][b1][b2] += sum over the pair-block's 4096-primary blocks (in
 // order, FP64) of the block Gram products.  Only macro tiles on or above the
 // diagonal are stored; C_m is symmetric.
@@ -309,117 +414,6 @@ __global__ void k_zeta_accum_mt(const CT* __restrict__ C, int nsub, MDims d, Row
   o[1] += im;
 }
 
-// ---- BF16x3: x = x0 + x1 + x2 with each xk the round-to-nearest-even bfloat16
-// of what is left, stored transposed ([column][row], rows padded to 32).
-__device__ __forceinline__ __bf16 to_bf16(float x) { return static_cast<__bf16>(x); }
-
-__global__ void k_split_bf16(ZetaArgs z, Dims d, int Kp) {
-  // one thread per (column c, row r), rows fastest
-  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long total = (long long)d.rowW * Kp;
-  if (idx >= total) return;
-  const int c = int(idx / Kp);
-  const int r = int(idx % Kp);
-  const long long Kv = valid_rows(z);
-  float x = 0.f, y = 0.f;
-  if (r < Kv) {
-    const double a = z.A[(z.sub_begin + r) * (long long)d.rowW + c];
-    const double wr = z.wsort[z.plist[z.row_begin + z.sub_begin + r]];
-    x = float(wr * a);
-    y = float(a);
-  }
-  __bf16* ops = static_cast<__bf16*>(z.ops);
-  const long long plane = (long long)d.rowW * Kp;
-  const long long at = (long long)c * Kp + r;
-  float rx = x, ry = y;
-  for (int k = 0; k < 3; ++k) {
-    const __bf16 hx = to_bf16(rx), hy = to_bf16(ry);
-    ops[k * plane + at] = hx;
-    ops[(3 + k) * plane + at] = hy;
-    rx -= float(hx);
-    ry -= float(hy);
-  }
-}
-
-__device__ __forceinline__ bf16x8_t load8(const __bf16* p) {
-  return *reinterpret_cast<const bf16x8_t*>(p);
-}
-
-// Products kept: (x0 y0), (x0 y1), (x1 y0), (x0 y2), (x1 y1), (x2 y0).
-__global__ __launch_bounds__(256) void k_gram_bf16x3(ZetaArgs z, Dims d, int Kp) {
-  const int wave = blockIdx.x * 4 + threadIdx.x / kWave;
-  const int lane = threadIdx.x % kWave;
-  const int ntile = d.tiles[d.nm];
-  if (wave >= ntile * kZetaSplitK) return;
-  const int s = wave / ntile;
-  int m, ti, tj;
-  tile_of(d, wave % ntile, m, ti, tj);
-  const int W = d.W[m];
-  const int i = ti * kTile + lane % 16, j = tj * kTile + lane % 16;
-  const int g = lane / 16;
-  const int per = ((Kp + 32 * kZetaSplitK - 1) / (32 * kZetaSplitK)) * 32;
-  const int k0 = s * per, k1 = min(Kp, k0 + per);
-  const __bf16* ops = static_cast<const __bf16*>(z.ops);
-  const long long plane = (long long)d.rowW * Kp;
-  const int ci = d.off[m] + min(i, W - 1), cj = d.off[m] + min(j, W - 1);
-  const __bf16* X0 = ops + (long long)ci * Kp;
-  const __bf16* Y0 = ops + 3 * plane + (long long)cj * Kp;
-  float4_t acc = {0.f, 0.f, 0.f, 0.f};
-  const bf16x8_t zero8 = {};
-  for (int k = k0; k < k1; k += 32) {
-    const int kk = k + 8 * g;
-    bf16x8_t x0 = load8(X0 + kk), x1 = load8(X0 + plane + kk), x2 = load8(X0 + 2 * plane + kk);
-    bf16x8_t y0 = load8(Y0 + kk), y1 = load8(Y0 + plane + kk), y2 = load8(Y0 + 2 * plane + kk);
-    if (i >= W) x0 = x1 = x2 = zero8;
-    if (j >= W) y0 = y1 = y2 = zero8;
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x2, y0, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1, y1, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0, y2, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1, y0, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0, y1, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0, y0, acc, 0, 0, 0);
-  }
-  float* C = z.C32 + (long long)s * d.csize + d.cw[m];
-  for (int r = 0; r < 4; ++r) {
-    const int ii = ti * kTile + 4 * g + r;
-    if (ii < W && j < W) C[ii * W + j] = acc[r];
-  }
-}
-
-// zeta[m][l][l'][b1][b2] += block contribution, summed over K slices in order.
-template <typename CT>
-__global__ void k_zeta_accum(const CT* __restrict__ C, Dims d, RowLayout L,
-                             double* __restrict__ zeta) {
-  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int nb = L.nb, nm = L.lmax + 1;
-  const long long per_m = (long long)nm * nm * nb * nb;
-  if (idx >= per_m * nm) return;
-  long long t = idx;
-  const int b2 = int(t % nb); t /= nb;
-  const int b1 = int(t % nb); t /= nb;
-  const int lp = int(t % nm); t /= nm;
-  const int l = int(t % nm); t /= nm;
-  const int m = int(t);
-  if (l < m || lp < m) return;
-  const int W = d.W[m];
-  const int P = L.pos(m, l, b1), Pp = L.pos(m, lp, b2);
-  double re = 0.0, im = 0.0;
-  for (int s = 0; s < kZetaSplitK; ++s) {
-    const CT* c = C + (long long)s * d.csize + d.cw[m];
-    if (m == 0) {
-      re += double(c[P * W + Pp]);
-    } else {
-      const int dm = L.d[m];
-      const int Q = dm + P, Qp = dm + Pp;
-      re += double(c[P * W + Pp]) + double(c[Q * W + Qp]);
-      im += double(c[Q * W + Pp]) - double(c[P * W + Qp]);
-    }
-  }
-  double* o = zeta + idx * 2;
-  o[0] += re;
-  o[1] += im;
-}
-
 }  // namespace
 
 int sum_wm2(const RowLayout& L) {
@@ -451,34 +445,14 @@ size_t zeta_partial_doubles(const RowLayout& L, long long PB) {
 
 // All blocks of 4096 primaries of a pair-block (z.sub_begin = 0, z.K = rows).
 hipError_t launch_zeta_pairblock(const ZetaArgs& z, hipStream_t st) {
-  if (z.prec == G3PCF_PREC_BF16X3) {
-    for (long long s0 = 0; s0 < z.K; s0 += kZetaBlock) {
-      ZetaArgs b = z;
-      b.sub_begin = s0;
-      b.K = int(std::min<long long>(kZetaBlock, z.K - s0));
-      const Dims d = make_dims(b.lay);
-      const int waves = d.tiles[d.nm] * kZetaSplitK;
-      const unsigned blocks = unsigned((waves + 3) / 4);
-      const int Kp = ((b.K + 31) / 32) * 32;
-      const long long total = (long long)d.rowW * Kp;
-      hipLaunchKernelGGL(k_split_bf16, dim3(unsigned((total + 255) / 256)), dim3(256), 0, st, b,
-                         d, Kp);
-      hipLaunchKernelGGL(k_gram_bf16x3, dim3(blocks), dim3(256), 0, st, b, d, Kp);
-      const long long entries = (long long)(b.lay.lmax + 1) * (b.lay.lmax + 1) *
-                                (b.lay.lmax + 1) * b.lay.nb * b.lay.nb;
-      hipLaunchKernelGGL((k_zeta_accum<float>), dim3(unsigned((entries + 255) / 256)), dim3(256),
-                         0, st, b.C32, d, b.lay, b.zeta);
-      hipError_t e = hipGetLastError();
-      if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
-  }
   const MDims d = make_mdims(z.lay);
   const int nsub = int((z.K + kZetaBlock - 1) / kZetaBlock);
   if (nsub <= 0) return hipSuccess;
   const dim3 grid(unsigned(d.mt[d.nm]), unsigned(nsub));
   if (z.prec == G3PCF_PREC_FP32)
     hipLaunchKernelGGL((k_gram_mt<float>), grid, dim3(256), 0, st, z, d, z.C64);
+  else if (z.prec == G3PCF_PREC_BF16X3)
+    hipLaunchKernelGGL(k_gram_bf16x3_mt, grid, dim3(256), 0, st, z, d, z.C64);
   else
     hipLaunchKernelGGL((k_gram_mt<double>), grid, dim3(256), 0, st, z, d, z.C64);
   hipError_t e = hipGetLastError();
