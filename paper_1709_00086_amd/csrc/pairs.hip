@@ -73,6 +73,10 @@ namespace {
 constexpr int kWavesPerBlock = 4;
 constexpr int kMaxRuns = 4 * kWave;  // runs of one chunk of 64 rows (<= 4 per row)
 constexpr int kRing = 2 * kWave;     // accepted pairs waiting for a full wave
+// Run-start marks: one bit per virtual candidate index, for a span of
+// kMarkSpan candidates of the run table at a time (64 windows).
+constexpr int kMarkSpan = 64 * kWave;
+constexpr int kMarkWords = kMarkSpan / 32;
 
 // A run of the table: g0 is the cell-order slot of its first galaxy minus the
 // run's first virtual candidate index (so candidate c of the run is slot
@@ -102,7 +106,8 @@ struct WaveLds {
   RunEntry<Real> run[kMaxRuns];
   V ring[kRing];               // (d_x, d_y, d_z, w) forward; (d_x, d_y, d_z, index) adjoint
   int ring_j[kRing];           // secondary index of a ring entry (when spilled)
-  int win[kWave];              // run starts inside the current candidate window
+  // bit c of the span: a run starts at virtual candidate index mbase + c
+  __attribute__((aligned(8))) unsigned marks[kMarkWords];
   // forward: the reduced sums (+1 padding slot); FP32 adjoint: the
   // shell's polynomial coefficients on their way into vector registers
   Real M[ADJ ? (SPINT ? kTermsSpin + 3 : 1) : kTermsCart + 1];
@@ -421,39 +426,65 @@ struct PairKernel {
     }
     total = uniform_int(__shfl(incl, kWave - 1));
     const int nrun = __popcll(m1) + __popcll(m2) + __popcll(m3) + __popcll(m4);
+    // marks of the first span [0, kMarkSpan)
+    clear_marks(W);
+    v = incl - tot;
+    for (int i = 0; i < 4; ++i) {
+      if (i < n_here && v < kMarkSpan) set_mark(W, v);
+      v += lenv[i];
+    }
     wave_lds_fence();
     return nrun;
+  }
+
+  static __device__ __forceinline__ void clear_marks(Lds& W) {
+    const int lane = threadIdx.x % kWave;
+    static_assert(kMarkWords == 2 * kWave, "two mark words per lane");
+    reinterpret_cast<unsigned long long*>(W.marks)[lane] = 0ull;
+    // LDS operations of one wave complete in order; the empty statement keeps
+    // the compiler from moving the marks' updates above the clear
+    asm volatile("" ::: "memory");
+  }
+  static __device__ __forceinline__ void set_mark(Lds& W, int c) {
+    __hip_atomic_fetch_or(&W.marks[c >> 5], 1u << (c & 31), __ATOMIC_RELAXED,
+                          __HIP_MEMORY_SCOPE_WAVEFRONT);
+  }
+  // Marks of the span starting at mbase, from the run starts in LDS.
+  static __device__ __forceinline__ void span_marks(Lds& W, int nrun, int mbase) {
+    const int lane = threadIdx.x % kWave;
+    wave_lds_fence();
+    clear_marks(W);
+    for (int r = lane; r < nrun; r += kWave) {
+      const int c = W.pre[r] - mbase;
+      if (c >= 0 && c < kMarkSpan) set_mark(W, c);
+    }
+    wave_lds_fence();
   }
 
   // Candidate of each lane in the window [v0, v0 + 64) of the chunk's runs
   // (lanes past the end repeat the last candidate).  Windows come in order:
   // kb is the run holding v0 - 1 on entry (-1 before the first window) and the
-  // run holding the window's last candidate on return.  The run starts are
-  // read from a register cache: lane i holds pre[kbase + i] (INT_MAX past the
-  // last run), kept at kbase <= kb + 1 and reloaded from kb + 1 when a window
-  // may reach past the cached runs.  Runs are never empty, so the starts that
-  // fall inside the window are distinct positions: they are marked in LDS,
-  // and a lane's run is kb plus the marks at or below its position.
+  // run holding the window's last candidate on return.  The run starts inside
+  // the window are the window's 64 bits of the marks (runs are never empty, so
+  // starts are distinct positions), and a lane's run is kb plus the marks at or
+  // below its position.  mbase is the first index of the span the marks hold.
   static __device__ __forceinline__ int map_window(Lds& W, int nrun, int total, int v0, int& kb,
-                                                   int& kbase, int& prec, Real ref[3]) {
+                                                   int& mbase, Real ref[3]) {
     const int lane = threadIdx.x % kWave;
     const int vc = min(v0 + lane, total - 1);
-    const int vend = min(v0 + kWave - 1, total - 1);
-    // all 64 cached runs start at or before the window's last candidate: the
-    // next run may too, so the cache moves up to the first run past kb
-    if (ballot(prec <= vend) == ~0ull && kbase + kWave < nrun && kb + 1 > kbase) {
-      kbase = kb + 1;
-      prec = (kbase + lane < nrun) ? W.pre[kbase + lane] : INT_MAX;
+    unsigned long long pm = 0;
+    if (v0 < total) {
+      if (v0 - mbase >= kMarkSpan) {
+        mbase = v0 & ~(kMarkSpan - 1);
+        span_marks(W, nrun, mbase);
+      }
+      const unsigned long long w =
+          reinterpret_cast<const unsigned long long*>(W.marks)[(v0 - mbase) >> 6];
+      pm = (static_cast<unsigned long long>(uniform_int(int(w >> 32))) << 32) |
+           static_cast<unsigned>(uniform_int(int(unsigned(w))));
     }
-    // LDS operations of one wave complete in order; the empty statements only
-    // keep the compiler from reordering the three accesses
-    W.win[lane] = 0;
-    asm volatile("" ::: "memory");
-    if (prec >= v0 && prec <= vend) W.win[prec - v0] = 1;
-    asm volatile("" ::: "memory");
-    const int f = W.win[lane];
-    const int k = kb + lanes_below(ballot(f != 0)) + f;
-    kb = __builtin_amdgcn_readlane(k, kWave - 1);
+    const int k = kb + lanes_below(pm) + int((pm >> lane) & 1ull);
+    kb += __popcll(pm);
     const RunEntry<Real> e = W.run[k];
     if constexpr (kF32) {
       ref[0] = e.rx;
@@ -538,8 +569,7 @@ struct PairKernel {
       int total = 0;
       const int nrun = build_runs(a, cs, P, r0sq, r1sq, c0, nyr, inv_nyr, rb, nrows, W, total);
       if (total == 0) continue;
-      int kb = -1, kbase = 0;
-      int prec = lane < nrun ? W.pre[lane] : INT_MAX;
+      int kb = -1, mbase = 0;
       // bin one window and append its accepted pairs to the ring; consume a
       // full wave of pairs when there is one
       auto step = [&](const V& q, const Real* rref, int j, int v0) {
@@ -600,13 +630,13 @@ struct PairKernel {
       // nothing.
       Real refa[3] = {P.pref[0], P.pref[1], P.pref[2]};
       Real refb[3] = {P.pref[0], P.pref[1], P.pref[2]};
-      int ja = map_window(W, nrun, total, 0, kb, kbase, prec, refa);
+      int ja = map_window(W, nrun, total, 0, kb, mbase, refa);
       V qa = load_galaxy(pos4, ja);
       for (int v0 = 0; v0 < total; v0 += 2 * kWave) {
-        const int jb = map_window(W, nrun, total, v0 + kWave, kb, kbase, prec, refb);
+        const int jb = map_window(W, nrun, total, v0 + kWave, kb, mbase, refb);
         const V qb = load_galaxy(pos4, jb);
         step(qa, refa, ja, v0);
-        ja = map_window(W, nrun, total, v0 + 2 * kWave, kb, kbase, prec, refa);
+        ja = map_window(W, nrun, total, v0 + 2 * kWave, kb, mbase, refa);
         qa = load_galaxy(pos4, ja);
         step(qb, refb, jb, v0 + kWave);
       }

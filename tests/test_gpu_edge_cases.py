@@ -1,7 +1,9 @@
 """Edge cases of the HIP path against the FP64 oracle (through the C ABI).
 
-* windows of 64 single-galaxy runs (the pair kernel's run-start cache moving
-  past a window's predecessor; catalogue and host replay in window_case.py);
+* windows of 64 single-galaxy runs (a run start at every position of a
+  window; catalogue and host replay in window_case.py);
+* blocks of 64 rows with more than 8192 candidates (the run-start marks are
+  rebuilt every 4096 candidates of a block; dense open box, window_case.py);
 * an open box with galaxies outside [box_lo, box_lo + box) (the outer cells
   hold every point beyond the box);
 * crowded cells with exact duplicates (the stable sort into cell order);
@@ -93,6 +95,34 @@ def test_windows_of_single_galaxy_runs(dev, precision, basis):
     assert e <= TOL[precision]
     # every separation is 85 +- 1e-3 from the primary: no shell-edge ambiguity
     assert pairs == pairs_ref
+    g = grad_gpu(cat, c, dev, precision, basis, mask)
+    eg = rel(g, g_ref)
+    say(f"  gradient {eg:.3e}")
+    assert eg <= (1e-10 if precision == "fp64" else 1e-4)
+
+
+@functools.lru_cache(maxsize=None)
+def dense_case(dtype):
+    cat, mask = WC.build_dense(np.dtype(dtype).type)
+    ref, pairs = oracle.zeta(cat, primary_mask=mask, return_pairs=True)
+    c = np.random.default_rng(49).standard_normal(C.zeta_shape(cat.lmax, cat.nbins))
+    g = oracle.grad(cat, c, primary_mask=mask)
+    return cat, mask, ref, pairs, c, g
+
+
+@pytest.mark.parametrize("precision,basis", MODES)
+def test_blocks_over_several_mark_spans(dev, precision, basis):
+    dtype = "float64" if precision == "fp64" else "float32"
+    say(f"case dense open box {precision} {basis}")
+    cat, mask, ref, pairs_ref, c, g_ref = dense_case(dtype)
+    z, pairs = run_gpu(cat, dev, precision, basis, mask)
+    e = rel(z, ref)
+    say(f"  zeta {e:.3e}, pairs {pairs} (oracle {pairs_ref})")
+    assert e <= TOL[precision]
+    if precision == "fp64":
+        assert pairs == pairs_ref
+    else:
+        assert abs(pairs - pairs_ref) <= 2 + 1e-6 * pairs_ref
     g = grad_gpu(cat, c, dev, precision, basis, mask)
     eg = rel(g, g_ref)
     say(f"  gradient {eg:.3e}")

@@ -11,9 +11,8 @@ def test_some_window_holds_64_single_galaxy_runs():
         blocks = WC.window_runs(cat)
         # every run of the shell's search is a single galaxy ...
         assert all(all(r == 1 for r in runs) for runs in blocks)
-        # ... and some block of 64 rows has more than 64 of them, so its first
-        # window of 64 candidates spans 64 runs and the next one starts past
-        # the 64 cached run starts
+        # ... and some block of 64 rows has more than 64 of them, so a window
+        # of 64 candidates spans 64 runs (a run start at every position)
         assert max(len(runs) for runs in blocks) > 64
         # each galaxy of the construction is at distance 85 from the primary,
         # in the middle of shell 8 ([80, 90)), far from both edges
@@ -22,3 +21,14 @@ def test_some_window_holds_64_single_galaxy_runs():
         near = d[d < 100.0]
         assert near.size == sum(len(r) for r in blocks)
         assert np.abs(near - 85.0).max() < 1e-3
+
+
+def test_dense_box_blocks_span_several_mark_spans():
+    cat, mask = WC.build_dense(np.float64)
+    assert int(mask.sum()) == 4
+    best = 0
+    for k in np.flatnonzero(mask):
+        for shell in (8, 9):
+            best = max(best, max(WC.block_totals(cat, int(k), shell)))
+    # a block of 64 rows with candidates in three spans of run-start marks
+    assert best > 2 * WC.MARK_SPAN

@@ -4,8 +4,9 @@ The pair kernel reads a shell's candidates as runs of cell-order slots: per
 (cy, cz) row of cells, the cells of the row that can hold a separation in the
 shell's annulus (the outer sphere's x-interval minus the inner sphere's, so up
 to two ranges per row), 64 rows at a time, and maps 64 candidates at a time to
-their runs.  A window of 64 candidates that spans 64 runs needs the run-start
-cache to move past the window's predecessor.  This module builds a catalogue
+their runs.  A window of 64 candidates that spans 64 runs has a run start at
+every position (all 64 of its run-start marks set), the extreme case of that
+mapping.  This module builds a catalogue
 in which one primary's annulus runs are all one galaxy long and more than 64
 of them fall into one block of rows, and it replays the grid and run
 construction on the host (same formulas as the library's cell grid and run
@@ -159,3 +160,46 @@ def window_runs(cat):
                     runs.append(cnt)
         blocks.append(runs)
     return blocks
+
+
+# ---- a dense open box: blocks of 64 rows with several spans of run-start marks
+# (the kernel marks run starts for 4096 candidates of a block at a time)
+
+DENSE_N = 250000
+MARK_SPAN = 4096
+
+
+def build_dense(dtype=np.float64, seed=47, nprim=4):
+    """Uniform galaxies in the open box [0, 260)^3 (R_max = 100, 10 shells);
+    primaries: the nprim galaxies nearest the box centre.  (catalogue, mask)"""
+    rng = np.random.default_rng(seed)
+    pos64 = rng.uniform(0.0, L, size=(DENSE_N, 3))
+    w = rng.uniform(0.5, 1.5, size=DENSE_N)
+    cat = C.Catalogue("dense_open_box", np.ascontiguousarray(pos64.astype(dtype)), w,
+                      (L, L, L), (0.0, 0.0, 0.0), False, RMAX, NBINS, 10, "z")
+    d = np.linalg.norm(pos64 - L / 2, axis=1)
+    mask = np.zeros(DENSE_N, np.uint8)
+    mask[np.argsort(d)[:nprim]] = 1
+    return cat, mask
+
+
+def block_totals(cat, k, shell):
+    """Candidates per block of 64 rows of galaxy k's search of `shell`
+    (host replay of the run construction, open box)."""
+    g = grid(cat.n, cat.box, cat.box_lo, cat.rmax, cat.periodic)
+    cx, cy, cz = cells_of(g, cat.pos)
+    rows = shell_rows(g, np.asarray(cat.pos[k], np.float64), shell, cat.nbins, cat.rmax)
+    key = cy.astype(np.int64) * (g["nc"][2] + 1) + cz
+    order = np.argsort(key, kind="stable")
+    ks, xs = key[order], cx[order]
+    totals = []
+    for b0 in range(0, len(rows), 64):
+        t = 0
+        for (ry, rz), ranges, _ in rows[b0:b0 + 64]:
+            kk = ry * (g["nc"][2] + 1) + rz
+            lo, hi = np.searchsorted(ks, kk), np.searchsorted(ks, kk, side="right")
+            row_x = xs[lo:hi]
+            for a, b in ranges:
+                t += int(np.count_nonzero((row_x >= a) & (row_x <= b)))
+        totals.append(t)
+    return totals
