@@ -139,9 +139,10 @@ def summarise_rocprof(args):
                 per.setdefault(counter, []).append(val)
             elif "copyBuffer" in name:
                 copy.setdefault(counter, []).append(val)
+    sources = args.sources or PAIR_KERNEL_SOURCES
     rec = {"kernel": args.label or args.kernel_regex,
-           "source_sha256": sources_sha256(PAIR_KERNEL_SOURCES),
-           "source_files": PAIR_KERNEL_SOURCES,
+           "source_sha256": sources_sha256(sources),
+           "source_files": sources,
            "counters_per_launch": {k: statistics.fmean(v) for k, v in sorted(per.items())},
            "launches_counted": {k: len(v) for k, v in sorted(per.items())},
            "commands": args.commands or []}
@@ -367,6 +368,9 @@ def main():
     ap.add_argument("--label", default=None)
     ap.add_argument("--copy-mib", type=int, default=0)
     ap.add_argument("--commands", nargs="*", default=None)
+    ap.add_argument("--sources", nargs="*", default=None,
+                    help="source files whose hash the record keeps (default: the pair "
+                         "kernel's)")
     ap.add_argument("--out", default=None)
     args = ap.parse_args()
     if args.summarise_rocprof:
