@@ -138,13 +138,18 @@ __device__ __forceinline__ int lanes_below(unsigned long long m) {
   return __builtin_amdgcn_mbcnt_hi(unsigned(m >> 32), __builtin_amdgcn_mbcnt_lo(unsigned(m), 0));
 }
 
+// Inclusive prefix sum over the 64 lanes with DPP moves only (no lane
+// addresses to keep live): row_shr 1, 2, 4 and 8 give every lane the sum of
+// its row up to itself (lanes shifted in from outside the row read 0), then
+// row_bcast 15 adds the last lane of rows 0 and 2 to rows 1 and 3, and
+// row_bcast 31 the last lane of row 1 (rows 0-1 by then) to rows 2 and 3.
 __device__ __forceinline__ int wave_incl_scan(int x) {
-  const int lane = threadIdx.x % kWave;
-#pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) {
-    const int y = __shfl_up(x, off);
-    if (lane >= off) x += y;
-  }
+  x += dpp_i<0x111, 0xF, 0xF>(x);
+  x += dpp_i<0x112, 0xF, 0xF>(x);
+  x += dpp_i<0x114, 0xF, 0xF>(x);
+  x += dpp_i<0x118, 0xF, 0xF>(x);
+  x += dpp_i<0x142, 0xA, 0xF>(x);
+  x += dpp_i<0x143, 0xC, 0xF>(x);
   return x;
 }
 
@@ -424,7 +429,7 @@ struct PairKernel {
         v += lenv[i];
       }
     }
-    total = uniform_int(__shfl(incl, kWave - 1));
+    total = uniform_int(__builtin_amdgcn_readlane(incl, kWave - 1));
     const int nrun = __popcll(m1) + __popcll(m2) + __popcll(m3) + __popcll(m4);
     // marks of the first span [0, kMarkSpan)
     clear_marks(W);
