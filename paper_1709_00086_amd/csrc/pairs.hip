@@ -454,6 +454,12 @@ struct PairKernel {
     __hip_atomic_fetch_or(&W.marks[c >> 5], 1u << (c & 31), __ATOMIC_RELAXED,
                           __HIP_MEMORY_SCOPE_WAVEFRONT);
   }
+  // The 64 marks from offset c (a multiple of 64) of the span, wave-uniform.
+  static __device__ __forceinline__ unsigned long long window_marks(const Lds& W, int c) {
+    const unsigned long long w = reinterpret_cast<const unsigned long long*>(W.marks)[c >> 6];
+    return (static_cast<unsigned long long>(uniform_int(int(w >> 32))) << 32) |
+           static_cast<unsigned>(uniform_int(int(unsigned(w))));
+  }
   // Marks of the span starting at mbase, from the run starts in LDS.
   static __device__ __forceinline__ void span_marks(Lds& W, int nrun, int mbase) {
     const int lane = threadIdx.x % kWave;
@@ -477,18 +483,22 @@ struct PairKernel {
                                                    int& mbase, Real ref[3]) {
     const int lane = threadIdx.x % kWave;
     const int vc = min(v0 + lane, total - 1);
+    // the window's 64 marks (none past the end); one test on the common
+    // path, where v0 is below both the end and the end of the marked span
     unsigned long long pm = 0;
-    if (v0 < total) {
-      if (v0 - mbase >= kMarkSpan) {
-        mbase = v0 & ~(kMarkSpan - 1);
-        span_marks(W, nrun, mbase);
-      }
-      const unsigned long long w =
-          reinterpret_cast<const unsigned long long*>(W.marks)[(v0 - mbase) >> 6];
-      pm = (static_cast<unsigned long long>(uniform_int(int(w >> 32))) << 32) |
-           static_cast<unsigned>(uniform_int(int(unsigned(w))));
+    if (__builtin_expect(v0 < min(total, mbase + kMarkSpan), 1)) {
+      pm = window_marks(W, v0 - mbase);
+    } else if (v0 < total) {
+      mbase = v0 & ~(kMarkSpan - 1);
+      span_marks(W, nrun, mbase);
+      pm = window_marks(W, v0 - mbase);
     }
-    const int k = kb + lanes_below(pm) + int((pm >> lane) & 1ull);
+    // the lane's own mark as the count's starting value (the mask itself
+    // selects it, one instruction)
+    int f;
+    asm("v_cndmask_b32_e64 %0, 0, 1, %1" : "=v"(f) : "s"(pm));
+    const int k = kb + __builtin_amdgcn_mbcnt_hi(unsigned(pm >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo(unsigned(pm), f));
     kb += __popcll(pm);
     const RunEntry<Real> e = W.run[k];
     if constexpr (kF32) {
