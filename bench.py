@@ -322,7 +322,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3", "fp64"])
+    ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16x3", "fp64"],
+                    help="fp32: FP32 pairs, FP32 MFMA zeta stage; bf16x3 (default): FP32 "
+                         "pairs, BF16x3-split MFMA zeta stage; fp64: FP64 throughout")
     ap.add_argument("--basis", default="spin", choices=["cartesian", "spin"])
     ap.add_argument("--forward-only", action="store_true",
                     help="time the forward pass only (not the contract's step)")
@@ -388,7 +390,7 @@ def main():
         args.no_cpu_baseline = True
         args.no_fp64_compare = True
     default_run = not (args.forward_only or args.keep_alm or args.batch or args.regions
-                       or args.distinct) and args.precision == "fp32"
+                       or args.distinct) and args.precision != "fp64"
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus > 1 or world > 1:
@@ -581,10 +583,12 @@ def main():
         # counted as the full square Gram
         zfl = ZETA_FLOPS_PER_PRIMARY * cat.n / (zeta_launch_ms * 1e-3) / 1e12
         zp = cfg.zeta_prec()
-        key = {_lib.PREC_FP32: "fp32_mfma_tflops", _lib.PREC_FP64: "fp64_mfma_tflops",
-               _lib.PREC_BF16X3: "fp32_mfma_tflops"}[zp]
+        # BF16x3 does six bfloat16 products per FP32-equivalent product
+        key, work = {_lib.PREC_FP32: ("fp32_mfma_tflops", 1), _lib.PREC_FP64: ("fp64_mfma_tflops", 1),
+                     _lib.PREC_BF16X3: ("bf16_mfma_tflops", 6)}[zp]
         out["zeta_stage"] = {"ms_per_pass": zeta_launch_ms, "tflops_full_square": zfl,
-                             "frac_of_mfma_peak": zfl / PEAK[key], "peak": key}
+                             "mfma_tflops": zfl * work,
+                             "frac_of_mfma_peak": zfl * work / PEAK[key], "peak": key}
 
     # the same seeded primary sample for the errors, the FP64 comparison and the
     # CPU baseline
@@ -676,9 +680,11 @@ def main():
     if default_run and not args.no_legs:
         reps = max(1, args.leg_steps)
         legs = {}
-        # BF16x3 zeta stage: FP32 pairs, each FP32 operand split into three
-        # bfloat16 terms, FP32 accumulation, FP64 sum across blocks
-        cfgb = config(cat, "bf16x3")
+        # the other FP32-path zeta stage: FP32 MFMA, or BF16x3 (each FP32
+        # operand split into three bfloat16 terms, FP32 accumulation, FP64 sum
+        # across blocks)
+        alt = "fp32" if args.precision == "bf16x3" else "bf16x3"
+        cfgb = config(cat, alt)
         api.zeta(pos, w, cfgb, out=zeta_out, workspace=ws)
         trb = _lib.Trace(capacity=1024)
         ts = []
@@ -689,7 +695,8 @@ def main():
             torch.cuda.synchronize()
             ts.append((time.perf_counter() - t) * 1e3)
         stb = stage_table(trb.read(), reps)
-        bleg = {"forward_ms": statistics.median(ts), "zeta_stage_ms": stb.get("zeta")}
+        bleg = {"precision": alt, "forward_ms": statistics.median(ts),
+                "zeta_stage_ms": stb.get("zeta")}
         if stb.get("zeta"):
             bleg["zeta_tflops_fp32_equivalent"] = (ZETA_FLOPS_PER_PRIMARY * cat.n /
                                                    (stb["zeta"] * 1e-3) / 1e12)
@@ -708,8 +715,8 @@ def main():
             else:
                 zsw[zp] = float(np.abs(zz - base).max() / np.abs(base).max())
         bleg["zeta_stage_err_vs_fp64_zeta_stage"] = zsw
-        legs["bf16x3"] = bleg
-        log(f"bf16x3 forward {bleg['forward_ms']:.1f} ms; zeta stage errors {zsw}")
+        legs["zeta_" + alt] = bleg
+        log(f"{alt} zeta stage: forward {bleg['forward_ms']:.1f} ms; zeta stage errors {zsw}")
         # the clustered observer-LOS catalogue and the adjoint catalogue, same step
         for key in ("c3", "c5"):
             t = time.time()
@@ -717,7 +724,7 @@ def main():
             gen = time.time() - t
             opos = torch.from_numpy(oc.pos).to(dev)
             ow = torch.from_numpy(oc.w).to(dev)
-            ocfg = config(oc, "fp32")
+            ocfg = config(oc, args.precision)
             oc_c = torch.from_numpy(C.loss_weights(oc.lmax, oc.nbins, seed=55)).to(dev)
             _, opairs = api.zeta(opos, ow, ocfg, out=None, workspace=ws, return_pairs=True)
 
@@ -728,7 +735,7 @@ def main():
             oms = median_ms(ostep, reps, torch)
             legs[oc.name] = {"ms_per_step": oms, "pairs_per_s": opairs / (oms * 1e-3),
                              "accepted_pairs": opairs, "step": "forward+backward",
-                             "precision": "fp32", "basis": args.basis}
+                             "precision": args.precision, "basis": args.basis}
             log(f"{oc.name}: {oms:.1f} ms per step, {opairs / (oms * 1e-3):.3e} pairs/s "
                 f"(generated in {gen:.1f} s)")
             del opos, ow

@@ -19,7 +19,9 @@
 // Because conj(Y_lm(u)) = sum_t c_{lm,t} mono_t(u) with the same monomials the
 // forward pass accumulates, the secondary term is a polynomial in u with
 // coefficients g_t(b) = sum_lm (Re c_{lm,t} Re H_lm(b) - Im c_{lm,t} Im H_lm(b)),
-// evaluated per pair by the pair kernel's adjoint mode.
+// evaluated per pair by the pair kernel's adjoint mode.  With FP64 pairs
+// k_adj_finish forms the primary terms and these coefficients here; with FP32
+// pairs the adjoint pair kernel forms both from the H rows itself.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -262,14 +264,16 @@ hipError_t launch_adj_matrix(const double* gz, const RowLayout& L, double* MHt,
   return hipGetLastError();
 }
 
-hipError_t launch_adj_coef(const AdjArgs& a, hipStream_t st) {
-  const AdjDims d = make_adj_dims(a.lay);
+hipError_t launch_h_gemm(const AdjArgs& a, hipStream_t st) {
   const HDims hd = make_hdims(a.lay);
   const long long row_tiles = (a.p_count + kHT - 1) / kHT;
   hipLaunchKernelGGL(k_h_gemm, dim3(unsigned(hd.ct[hd.nm]), unsigned(row_tiles)), dim3(256), 0,
                      st, a.A, a.MHt, hd, a.nprim, a.p_begin, a.p_count, a.H);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_finish(const AdjArgs& a, hipStream_t st) {
+  const AdjDims d = make_adj_dims(a.lay);
   const size_t shm = size_t(kFinThreads + d.rowW) * sizeof(double);
   hipLaunchKernelGGL(k_adj_finish, dim3(unsigned(a.p_count)), dim3(kFinThreads), shm, st, a, d);
   return hipGetLastError();

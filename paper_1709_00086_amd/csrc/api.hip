@@ -118,10 +118,11 @@ Ws plan(const g3pcf_problem& p, int backward, int64_t pb_max = kPairBlockMax,
   w.degD = take(deg ? size_t(p.nbins) * (2 * p.lmax + 1) * 8 : 0);
   w.degP = take(deg ? deg_partial_doubles(w.PB, p.nbins, p.lmax) * 8 : 0);
   if (backward) {
-    // adjoint coefficients per primary and shell: the FP32 adjoint always
-    // takes the 121 spin-Chebyshev terms, the FP64 one the forward's basis
-    const int T = (p.basis == G3PCF_BASIS_SPIN || !fp64) ? kTermsSpin : kTermsCart;
-    w.gcoef = take(size_t(w.PB) * p.nbins * T * 8);
+    // adjoint coefficients per primary and shell in the forward's basis (FP64
+    // pair path only: the FP32 adjoint pair kernel forms its spin-Chebyshev
+    // coefficients from the H rows)
+    const int T = (p.basis == G3PCF_BASIS_SPIN) ? kTermsSpin : kTermsCart;
+    w.gcoef = take(fp64 ? size_t(w.PB) * p.nbins * T * 8 : 0);
     w.gsort = take(size_t(n) * 8);
     w.gsort32 = take(fp64 ? 0 : size_t(n) * 4);  // FP32 secondary terms (FP32 pair path)
     w.mht = take(adj_matrix_doubles(w.lay) * 8);
@@ -743,6 +744,7 @@ int g3pcf_backward(const g3pcf_problem* prob, const double* grad_zeta, double* g
   const ConvTable* tab = nullptr;
   if ((e = conv_table_device(adj_table, &tab)) != hipSuccess) return hip_fail(e, "table address");
   a.gcoef = at<double>(ws, w.gcoef);
+  a.H = at<double>(ws, w.hrows);
   a.grad_w = gsort;
   a.grad_w32 = gsort32;
   for (int64_t b0 = 0; b0 < p.n; b0 += w.PB) {
@@ -775,7 +777,9 @@ int g3pcf_backward(const g3pcf_problem* prob, const double* grad_zeta, double* g
     j.H = at<double>(ws, w.hrows);
     {
       StageScope sc(p.trace, G3PCF_STAGE_ADJ_COEF, st);
-      if ((e = launch_adj_coef(j, st)) != hipSuccess) return hip_fail(e, "adjoint coefficients");
+      if ((e = launch_h_gemm(j, st)) != hipSuccess) return hip_fail(e, "adjoint GEMM");
+      if (fp64 && (e = launch_adj_finish(j, st)) != hipSuccess)
+        return hip_fail(e, "adjoint coefficients");
     }
     a.pairs = &c->pairs_adj;
     {

@@ -133,7 +133,8 @@ struct PairArgs {
   double* A;                 // [p_count][W] a_lm rows (forward)
   RowLayout lay;
   // adjoint
-  const double* gcoef;       // [p_count][nbins][T] monomial-space adjoint coefficients
+  const double* gcoef;       // [p_count][nbins][T] monomial-space adjoint coefficients (FP64 pairs)
+  const double* H;           // [p_count][W] H rows (FP32 pairs: converted per shell in the kernel)
   const int* perm;           // [n] slot -> original index
   double* grad_w;            // [n] cell order: FP64 pair path (secondary terms added atomically)
   float* grad_w32;           // [n] cell order: FP32 pair path (secondary terms added atomically)
@@ -219,7 +220,11 @@ struct AdjArgs {
 };
 size_t adj_matrix_doubles(const RowLayout& L);
 hipError_t launch_adj_matrix(const double* gz, const RowLayout& L, double* MHt, hipStream_t st);
-hipError_t launch_adj_coef(const AdjArgs& a, hipStream_t st);
+// H = X M_H^T (k_h_gemm) and, for the FP64 pair path, the primary terms and
+// the per-shell monomial coefficients (k_adj_finish); the FP32 adjoint pair
+// kernel forms both from H itself.
+hipError_t launch_h_gemm(const AdjArgs& a, hipStream_t st);
+hipError_t launch_adj_finish(const AdjArgs& a, hipStream_t st);
 // grad[perm[s]] (=|+=) gs[s] (+ gs32[s] when gs32 is not null); NaN instead
 // when fp_saved is not null and *fp_saved != *fp_now
 hipError_t launch_unpermute(const double* gs, const float* gs32, const int* perm, int64_t n,

@@ -813,14 +813,11 @@ struct PairKernel {
       }
       wave_lds_fence();
     } else {
-      // the shell's coefficients, read through the scalar cache (uniform)
-      const CoefPtr gc = (CoefPtr)(a.gcoef + (row * a.nbins + b) * kTerms);
       if constexpr (kSpinT) {
-        // FP32: Chebyshev-basis coefficients, converted once per shell
-        // and staged through LDS (one vector load per lane, then broadcast
-        // reads) into vector registers; FP32 polynomial and FP32 atomics
-        const double* gv = a.gcoef + (row * a.nbins + b) * kTerms;
-        for (int t = lane; t < kTermsSpin; t += kWave) W.M[t] = float(gv[t]);
+        // FP32: Chebyshev-basis coefficients, formed from the H row once per
+        // shell and staged through LDS (broadcast reads) into vector
+        // registers; FP32 polynomial and FP32 atomics
+        shell_coefficients(a, W, row, b);
         wave_lds_fence();
         SpinTPoly poly;
         poly.load(W.M);
@@ -846,6 +843,8 @@ struct PairKernel {
             });
         if (nout > 0) flush_terms(a, W, nout);
       } else {
+        // the shell's coefficients, read through the scalar cache (uniform)
+        const CoefPtr gc = (CoefPtr)(a.gcoef + (row * a.nbins + b) * kTerms);
         got = search_shell<MINIMG, false>(a, W, pos4, P, b, r0, r1,
                                           [&](const V& e, int, bool valid) {
                                             Real ux, uy, uz;
@@ -939,6 +938,7 @@ struct PairKernel {
 
       double w_prim = 0.0;
       if constexpr (ADJOINT) w_prim = a.wsort[slot];
+      if constexpr (kSpinT) primary_term(a, row, slot);
 
       for (int b = 0; b < nb; ++b) {
         // annulus of shell b, widened by the search margin on both sides
@@ -1045,6 +1045,59 @@ struct PairKernel {
     const int lane = threadIdx.x % kWave;
     const int nd = 2 * a.lmax + 1;
     if (lane < nd) a.A[row * a.lay.W + b * nd + lane] = double(W.M[lane]);
+  }
+
+  // FP32 adjoint, per primary: its term as a primary, Re(a^T H) / 2 in FP64
+  // over its A and H rows (the imaginary half of each m >= 1 block with a
+  // minus sign), added to its FP64 gradient entry (one wave per primary).
+  static __device__ __forceinline__ void primary_term(const PairArgs& a, long long row, int slot) {
+    const int lane = threadIdx.x % kWave;
+    const double* x = a.A + row * a.lay.W;
+    const double* h = a.H + row * a.lay.W;
+    double s = 0.0;
+    for (int m = 0; m <= a.lay.lmax; ++m) {
+      const int off = a.lay.off[m], wm = a.lay.wm[m], dm = a.lay.d[m];
+      for (int j = lane; j < wm; j += kWave) {
+        const double v = x[off + j] * h[off + j];
+        s += (m > 0 && j >= dm) ? -v : v;
+      }
+    }
+    s = wave_sum(s);
+    if (lane == kWave - 1) a.grad_w[slot] += 0.5 * s;
+  }
+
+  // FP32 adjoint, per primary and shell b: the 121 coefficients of the
+  // polynomial in (x - i y)^m T_n(z), g_t = sum over the spin-Chebyshev
+  // table's entries (t, lm) of Re c Re H_lm(b) - Im c Im H_lm(b), formed in
+  // FP64 and stored to LDS as FP32 (one or two terms a lane).  The shell's
+  // 121 H values are first staged in the table's output order, the
+  // imaginary parts negated and l > l_max as zero (one load a lane, all in
+  // flight together), in the ring's LDS, which is empty between shells.
+  static __device__ __forceinline__ void shell_coefficients(const PairArgs& a, Lds& W,
+                                                            long long row, int b) {
+    const int lane = threadIdx.x % kWave;
+    const double* h = a.H + row * a.lay.W;
+    const ConvTable& t = g_conv[G3PCF_BASIS_SPIN_T];
+    double* hs = reinterpret_cast<double*>(W.ring);
+    static_assert(sizeof(W.ring) >= kTermsSpin * sizeof(double), "staging fits the ring");
+    for (int o = lane; o < kTermsSpin; o += kWave) {
+      const int l = t.out_l[o], m = t.out_m[o];
+      const bool im = t.out_part[o] != 0;
+      double v = 0.0;
+      if (l <= a.lay.lmax) {
+        v = h[a.lay.off[m] + a.lay.pos(m, l, b) + (im ? a.lay.d[m] : 0)];
+        if (im) v = -v;
+      }
+      hs[o] = v;
+    }
+    wave_lds_fence();
+    for (int term = lane; term < kTermsSpin; term += kWave) {
+      double s = 0.0;
+      const int e1 = t.trowptr[term + 1];
+#pragma unroll 4
+      for (int e = t.trowptr[term]; e < e1; ++e) s = __builtin_fma(t.tcoef[e], hs[t.tout[e]], s);
+      W.M[term] = float(s);
+    }
   }
 
   // The buffered secondary terms of the FP32 adjoint into the FP32

@@ -132,6 +132,15 @@ def test_full_zeta_properties(dev, name):
     e32 = rel(z, z64)
     say(f"  full fp32 vs fp64: {e32:.3e}")
     assert e32 <= 1e-5
+    # the benchmark's default form: FP32 pairs, BF16x3 zeta stage over every
+    # block of primaries
+    zb, pbf = run(cat, dev, "bf16x3", "spin")
+    herm, im0, neg, zero_ok = check_properties(zb, cat.lmax, cat.nbins, f"{name} bf16x3 spin")
+    assert herm <= 1e-6 and im0 <= 1e-6 and neg <= 1e-6 and zero_ok
+    assert pbf == pairs
+    eb = rel(zb, z64)
+    say(f"  full bf16x3 vs fp64: {eb:.3e}")
+    assert eb <= 1e-5
 
 
 def test_zeta_stage_sweep_across_blocks(dev):
