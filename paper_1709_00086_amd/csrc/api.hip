@@ -93,7 +93,7 @@ Ws plan(const g3pcf_problem& p, int backward, int64_t pb_max = kPairBlockMax,
     at += up(std::max<size_t>(bytes, 1));
     return o;
   };
-  w.pos4 = take(size_t(n) * rb);
+  w.pos4 = take(size_t(n + kSentinel) * rb);
   w.tmp4 = take(size_t(n) * rb);
   w.cid = take(size_t(n) * 4);
   w.perm = take(size_t(n) * 4);
@@ -237,6 +237,7 @@ PairArgs pair_args(const g3pcf_problem& p, const Ws& w, void* ws) {
   PairArgs a{};
   Counters* c = at<Counters>(ws, w.counters);
   a.pos4 = at<void>(ws, w.pos4);
+  a.sentinel = int(p.n);
   a.cell_start = at<int>(ws, w.cell_start);
   a.plist = at<int>(ws, w.plist);
   a.nprim = &c->nprim;

@@ -173,13 +173,21 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(
   }
 }
 
-// Cell-order arrays from the sorted original indices.
+// Cell-order arrays from the sorted original indices, and the kSentinel NaN
+// entries after them.
 template <typename V4>
 __global__ void k_gather_sorted(const V4* __restrict__ in4, const int* __restrict__ perm,
                                 int64_t n, const double* __restrict__ w,
                                 V4* __restrict__ out4, double* __restrict__ wsort) {
   const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (s >= n) return;
+  if (s >= n) {
+    if (s < n + kSentinel) {
+      using T = decltype(out4[0].x);
+      const T nan = T(__builtin_nan(""));
+      out4[s] = V4{nan, nan, nan, nan};
+    }
+    return;
+  }
   const int i = perm[s];
   out4[s] = in4[i];
   wsort[s] = w[i];
@@ -468,12 +476,14 @@ hipError_t launch_cells(const g3pcf_problem& p, const Grid& g, const CellBufs& b
     kin = kout;
     vin = vout;
   }
+  // the gather also writes the kSentinel NaN entries after the catalogue
+  const unsigned ng = blocks_for(n + kSentinel, 256);
   if (fp64)
-    hipLaunchKernelGGL((k_gather_sorted<double4>), dim3(nb), dim3(256), 0, st,
+    hipLaunchKernelGGL((k_gather_sorted<double4>), dim3(ng), dim3(256), 0, st,
                        static_cast<const double4*>(b.stage4), b.perm, n, p.w,
                        static_cast<double4*>(b.pos4), b.wsort);
   else
-    hipLaunchKernelGGL((k_gather_sorted<float4>), dim3(nb), dim3(256), 0, st,
+    hipLaunchKernelGGL((k_gather_sorted<float4>), dim3(ng), dim3(256), 0, st,
                        static_cast<const float4*>(b.stage4), b.perm, n, p.w,
                        static_cast<float4*>(b.pos4), b.wsort);
   return hipGetLastError();

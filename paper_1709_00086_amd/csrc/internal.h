@@ -26,6 +26,10 @@ constexpr int kBasisDeg = 3;
 constexpr int kTermsDeg = 2 * kDeg + 1;                               // 21
 constexpr int kMaxBins = 32;
 constexpr int kWave = 64;
+// Entries after the catalogue in the cell-ordered position array, every
+// coordinate NaN: the FP32 pair search maps the lanes of a window past the
+// end of its candidates onto them, and no shell test accepts a NaN distance.
+constexpr int kSentinel = kWave;
 constexpr int kOutPerBin = (kDeg + 1) * (kDeg + 1);  // real a_lm outputs per shell (121)
 
 // Rows of A (primaries) reduced per Gram product on MFMA.
@@ -106,7 +110,8 @@ RowLayout make_layout(int lmax, int nb);
 
 // Arguments of the pair kernels (forward accumulation and adjoint scatter).
 struct PairArgs {
-  const void* pos4;          // [n] (x, y, z, w) in cell order, float4 or double4
+  const void* pos4;          // [n + kSentinel] (x, y, z, w) in cell order, float4 or double4
+  int sentinel;              // slot of the first NaN entry (n)
   const int* cell_start;     // [ncell + 1]
   const int* plist;          // [*nprim] primary slots in cell order
   const long long* nprim;    // device scalar: number of primaries
@@ -144,7 +149,7 @@ struct PairArgs {
 // ---- launchers (each returns hipGetLastError after the launch) ----
 // Buffers of the cell-list stage (all device, n = galaxies).
 struct CellBufs {
-  void* pos4;          // [n] out: cell-order (x, y, z, w), float4 or double4
+  void* pos4;          // [n + kSentinel] out: cell-order (x, y, z, w), float4 or double4, then NaN
   void* stage4;        // [n] scratch: the same values in input order
   int* cell_start;     // [ncell + 1] out
   int* cell_count;     // [ncell + 1] scratch

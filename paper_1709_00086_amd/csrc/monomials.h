@@ -111,8 +111,10 @@ __device__ __forceinline__ double row_sum(double v) {
   return v;
 }
 
-// Given row sums of four values a, e, b, f (rows 0..3 of each), return a
-// value whose row 0 holds the total of a, row 1 of e, row 2 of b, row 3 of f:
+// Fold four values a, e, b, f across rows: lane i of row 0 of the result
+// holds a summed over lanes i, i + 16, i + 32 and i + 48, row 1 the same for
+// e, row 2 for b, row 3 for f, so a row sum of the result gives the four
+// totals (and given row sums as inputs, the result holds the totals):
 // permlane32_swap exchanges the upper half of its first operand with the
 // lower half of its second, permlane16_swap the odd rows of its first with the
 // even rows of its second.

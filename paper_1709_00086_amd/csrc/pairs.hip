@@ -102,8 +102,8 @@ constexpr int kOutBuf = 8 * kWave;
 template <typename Real, bool ADJ, bool SPINT = false>
 struct WaveLds {
   using V = typename V4<Real>::T;
-  int pre[kMaxRuns];           // first virtual candidate index of each run
-  RunEntry<Real> run[kMaxRuns];
+  int pre[kMaxRuns + 1];       // first virtual candidate index of each run
+  alignas(16) RunEntry<Real> run[kMaxRuns + 1];  // (+1: the FP32 search's sentinel run)
   V ring[kRing];               // (d_x, d_y, d_z, w) forward; (d_x, d_y, d_z, index) adjoint
   int ring_j[kRing];           // secondary index of a ring entry (when spilled)
   // bit c of the span: a run starts at virtual candidate index mbase + c
@@ -431,6 +431,17 @@ struct PairKernel {
     }
     total = uniform_int(__builtin_amdgcn_readlane(incl, kWave - 1));
     const int nrun = __popcll(m1) + __popcll(m2) + __popcll(m3) + __popcll(m4);
+    if constexpr (kF32) {
+      // the sentinel run after the last one: the lanes of a window past the
+      // last candidate map onto the NaN entries after the catalogue
+      if (lane == 0) {
+        W.pre[nrun] = total;
+        RunEntry<Real> e;
+        e.g0 = a.sentinel - total;
+        e.rx = e.ry = e.rz = 0.0f;
+        W.run[nrun] = e;
+      }
+    }
     // marks of the first span [0, kMarkSpan)
     clear_marks(W);
     v = incl - tot;
@@ -438,6 +449,7 @@ struct PairKernel {
       if (i < n_here && v < kMarkSpan) set_mark(W, v);
       v += lenv[i];
     }
+    if (kF32 && lane == 0 && total < kMarkSpan) set_mark(W, total);
     wave_lds_fence();
     return nrun;
   }
@@ -460,20 +472,24 @@ struct PairKernel {
     return (static_cast<unsigned long long>(uniform_int(int(w >> 32))) << 32) |
            static_cast<unsigned>(uniform_int(int(unsigned(w))));
   }
-  // Marks of the span starting at mbase, from the run starts in LDS.
+  // Marks of the span starting at mbase, from the run starts in LDS (and the
+  // FP32 search's sentinel run).
   static __device__ __forceinline__ void span_marks(Lds& W, int nrun, int mbase) {
     const int lane = threadIdx.x % kWave;
     wave_lds_fence();
     clear_marks(W);
-    for (int r = lane; r < nrun; r += kWave) {
+    const int nr = kF32 ? nrun + 1 : nrun;
+    for (int r = lane; r < nr; r += kWave) {
       const int c = W.pre[r] - mbase;
       if (c >= 0 && c < kMarkSpan) set_mark(W, c);
     }
     wave_lds_fence();
   }
 
-  // Candidate of each lane in the window [v0, v0 + 64) of the chunk's runs
-  // (lanes past the end repeat the last candidate).  Windows come in order:
+  // Candidate of each lane in the window [v0, v0 + 64) of the chunk's runs.
+  // Lanes past the end: FP32, one of the NaN entries after the catalogue
+  // (through the sentinel run, whose start at `total` is marked like the
+  // others); FP64, the last candidate again.  Windows come in order:
   // kb is the run holding v0 - 1 on entry (-1 before the first window) and the
   // run holding the window's last candidate on return.  The run starts inside
   // the window are the window's 64 bits of the marks (runs are never empty, so
@@ -482,9 +498,9 @@ struct PairKernel {
   static __device__ __forceinline__ int map_window(Lds& W, int nrun, int total, int v0, int& kb,
                                                    int& mbase, Real ref[3]) {
     const int lane = threadIdx.x % kWave;
-    const int vc = min(v0 + lane, total - 1);
-    // the window's 64 marks (none past the end); one test on the common
-    // path, where v0 is below both the end and the end of the marked span
+    int vc = kF32 ? v0 + lane : min(v0 + lane, total - 1);
+    // the window's 64 marks; one test on the common path, where v0 is below
+    // both the end and the end of the marked span
     unsigned long long pm = 0;
     if (__builtin_expect(v0 < min(total, mbase + kMarkSpan), 1)) {
       pm = window_marks(W, v0 - mbase);
@@ -492,6 +508,10 @@ struct PairKernel {
       mbase = v0 & ~(kMarkSpan - 1);
       span_marks(W, nrun, mbase);
       pm = window_marks(W, v0 - mbase);
+    } else if constexpr (kF32) {
+      // a window past the end: every lane on the sentinel run's entries
+      kb = nrun;
+      vc = total + lane;
     }
     // the lane's own mark as the count's starting value (the mask itself
     // selects it, one instruction)
@@ -588,7 +608,6 @@ struct PairKernel {
       // bin one window and append its accepted pairs to the ring; consume a
       // full wave of pairs when there is one
       auto step = [&](const V& q, const Real* rref, int j, int v0) {
-        const bool valid = v0 + lane < total;
         Real d[3];
         bool acc;
         unsigned long long m;
@@ -605,12 +624,14 @@ struct PairKernel {
           d[0] = dx;
           d[1] = dy;
           d[2] = dz;
-          acc = valid & (r2 > lo2) & (r2 < hi2);  // no short circuit: no branches
+          // no short circuit: no branches; lanes past the end hold NaN and
+          // fail both tests
+          acc = (r2 > lo2) & (r2 < hi2);
           m = ballot(acc);
         } else {
           double r2;
           const int bin = P.bin64.classify(q, P.p, d, r2);
-          acc = valid && bin == b;
+          acc = (v0 + lane < total) && bin == b;
           m = ballot(acc);
         }
         if (acc) {
@@ -641,8 +662,8 @@ struct PairKernel {
       };
       // two windows in flight: while one is binned the other's loads are
       // outstanding (the buffers alternate, so no copy waits on a load).
-      // Windows past the end map every lane to the last candidate and accept
-      // nothing.
+      // Windows past the end accept nothing (FP32: every lane on a NaN
+      // entry; FP64: on the last candidate, rejected by the index test).
       Real refa[3] = {P.pref[0], P.pref[1], P.pref[2]};
       Real refb[3] = {P.pref[0], P.pref[1], P.pref[2]};
       int ja = map_window(W, nrun, total, 0, kb, mbase, refa);
@@ -983,9 +1004,11 @@ struct PairKernel {
     P.Rm[8] = Real(1.0 - vv * f);
   }
 
-  // Wave sums of a chunk's accumulators into W.M, four at a time: row sums by
-  // DPP, then one fold across rows leaves the four totals in rows 0..3, and
-  // every lane stores its row's total (16 lanes write the same value).
+  // Wave sums of a chunk's accumulators into W.M, four at a time: one fold
+  // across rows first (each lane of row r then holds four lanes' worth of
+  // value r), then row sums by DPP leave the four totals in rows 0..3, and
+  // every lane stores its row's total (16 lanes write the same value): ten
+  // instructions per four values instead of 22 with the row sums first.
   template <class Chunk>
   static __device__ __forceinline__ void reduce_store(Lds& W, Chunk& ch) {
     constexpr int NT = Chunk::NT;
@@ -997,12 +1020,11 @@ struct PairKernel {
     static_for<(NT + 3) / 4>([&](auto gc) {
       constexpr int g = decltype(gc)::value;
       constexpr int i0 = 4 * g, i1 = 4 * g + 1, i2 = 4 * g + 2, i3 = 4 * g + 3;
-      const Real a = row_sum(ch.acc[i0]);
       Real e = Real(0), b = Real(0), f = Real(0);
-      if constexpr (i1 < NT) e = row_sum(ch.acc[i1]);
-      if constexpr (i2 < NT) b = row_sum(ch.acc[i2]);
-      if constexpr (i3 < NT) f = row_sum(ch.acc[i3]);
-      const Real tot = fold4(a, e, b, f);
+      if constexpr (i1 < NT) e = ch.acc[i1];
+      if constexpr (i2 < NT) b = ch.acc[i2];
+      if constexpr (i3 < NT) f = ch.acc[i3];
+      const Real tot = row_sum(fold4(ch.acc[i0], e, b, f));
       constexpr int ta = Chunk::term_of(i0);
       constexpr int te = (i1 < NT) ? Chunk::term_of(i1) : kJunk;
       constexpr int tb = (i2 < NT) ? Chunk::term_of(i2) : kJunk;
