@@ -107,7 +107,7 @@ struct WaveLds {
   V ring[kRing];               // (d_x, d_y, d_z, w) forward; (d_x, d_y, d_z, index) adjoint
   int ring_j[kRing];           // secondary index of a ring entry (when spilled)
   // bit c of the span: a run starts at virtual candidate index mbase + c
-  __attribute__((aligned(8))) unsigned marks[kMarkWords];
+  __attribute__((aligned(16))) unsigned marks[kMarkWords];
   // forward: the reduced sums (+1 padding slot); FP32 adjoint: the
   // shell's polynomial coefficients on their way into vector registers
   Real M[ADJ ? (SPINT ? kTermsSpin + 3 : 1) : kTermsCart + 1];
@@ -472,6 +472,17 @@ struct PairKernel {
     return (static_cast<unsigned long long>(uniform_int(int(w >> 32))) << 32) |
            static_cast<unsigned>(uniform_int(int(unsigned(w))));
   }
+  // The marks of two adjacent windows from offset c (a multiple of 128) of
+  // the span, wave-uniform, in one LDS read.
+  static __device__ __forceinline__ void window_marks2(const Lds& W, int c,
+                                                       unsigned long long& m0,
+                                                       unsigned long long& m1) {
+    const uint4 q = reinterpret_cast<const uint4*>(W.marks)[c >> 7];
+    m0 = (static_cast<unsigned long long>(uniform_int(int(q.y))) << 32) |
+         static_cast<unsigned>(uniform_int(int(q.x)));
+    m1 = (static_cast<unsigned long long>(uniform_int(int(q.w))) << 32) |
+         static_cast<unsigned>(uniform_int(int(q.z)));
+  }
   // Marks of the span starting at mbase, from the run starts in LDS (and the
   // FP32 search's sentinel run).
   static __device__ __forceinline__ void span_marks(Lds& W, int nrun, int mbase) {
@@ -495,19 +506,34 @@ struct PairKernel {
   // the window are the window's 64 bits of the marks (runs are never empty, so
   // starts are distinct positions), and a lane's run is kb plus the marks at or
   // below its position.  mbase is the first index of the span the marks hold.
+  // Windows come in pairs, an even one (v0 a multiple of 128) and the odd one
+  // after it, in the same span: the even one reads both windows' marks and
+  // leaves the odd one's in nextm.
+  template <bool ODD>
   static __device__ __forceinline__ int map_window(Lds& W, int nrun, int total, int v0, int& kb,
-                                                   int& mbase, Real ref[3]) {
+                                                   int& mbase, Real ref[3],
+                                                   unsigned long long& nextm) {
     const int lane = threadIdx.x % kWave;
     int vc = kF32 ? v0 + lane : min(v0 + lane, total - 1);
     // the window's 64 marks; one test on the common path, where v0 is below
     // both the end and the end of the marked span
     unsigned long long pm = 0;
     if (__builtin_expect(v0 < min(total, mbase + kMarkSpan), 1)) {
-      pm = window_marks(W, v0 - mbase);
+      if constexpr (ODD) {
+        pm = nextm;
+      } else {
+        window_marks2(W, v0 - mbase, pm, nextm);
+      }
     } else if (v0 < total) {
+      // a new span starts at an even window (spans hold 64 windows), so an
+      // odd window below the end is always in its even window's span
       mbase = v0 & ~(kMarkSpan - 1);
       span_marks(W, nrun, mbase);
-      pm = window_marks(W, v0 - mbase);
+      if constexpr (ODD) {
+        pm = window_marks(W, v0 - mbase);
+      } else {
+        window_marks2(W, v0 - mbase, pm, nextm);
+      }
     } else if constexpr (kF32) {
       // a window past the end: every lane on the sentinel run's entries
       kb = nrun;
@@ -598,7 +624,7 @@ struct PairKernel {
       lo2 = a.r2_lo[b];
       hi2 = a.r2_hi[b];
     }
-    int head = 0, cnt = 0;
+    int cnt = 0;
     unsigned accepted = 0;
     for (int rb = 0; rb < nrows; rb += kWave) {
       int total = 0;
@@ -644,7 +670,7 @@ struct PairKernel {
           } else {
             ent.w = q.w;
           }
-          const int slot = (head + cnt + lanes_below(m)) & (kRing - 1);
+          const int slot = cnt + lanes_below(m);  // below kRing: cnt < kWave here
           W.ring[slot] = ent;
           if constexpr (SPILL) W.ring_j[slot] = j;
         }
@@ -652,11 +678,18 @@ struct PairKernel {
         cnt += got;
         accepted += unsigned(got);
         if (cnt >= kWave) {
+          // the first wave of pairs out, the rest (fewer than kWave) moved to
+          // the front, so that slots need no wrap-around
           wave_lds_fence();
-          const V ent = W.ring[(head + lane) & (kRing - 1)];
-          const int jj = SPILL ? W.ring_j[(head + lane) & (kRing - 1)] : 0;
+          const V ent = W.ring[lane];
+          const V rest = W.ring[kWave + lane];
+          int jj = 0;
+          if constexpr (SPILL) {
+            jj = W.ring_j[lane];
+            W.ring_j[lane] = W.ring_j[kWave + lane];
+          }
+          W.ring[lane] = rest;
           consume(ent, jj, true);
-          head = (head + kWave) & (kRing - 1);
           cnt -= kWave;
         }
       };
@@ -666,13 +699,14 @@ struct PairKernel {
       // entry; FP64: on the last candidate, rejected by the index test).
       Real refa[3] = {P.pref[0], P.pref[1], P.pref[2]};
       Real refb[3] = {P.pref[0], P.pref[1], P.pref[2]};
-      int ja = map_window(W, nrun, total, 0, kb, mbase, refa);
+      unsigned long long nextm = 0;
+      int ja = map_window<false>(W, nrun, total, 0, kb, mbase, refa, nextm);
       V qa = load_galaxy(pos4, ja);
       for (int v0 = 0; v0 < total; v0 += 2 * kWave) {
-        const int jb = map_window(W, nrun, total, v0 + kWave, kb, mbase, refb);
+        const int jb = map_window<true>(W, nrun, total, v0 + kWave, kb, mbase, refb, nextm);
         const V qb = load_galaxy(pos4, jb);
         step(qa, refa, ja, v0);
-        ja = map_window(W, nrun, total, v0 + 2 * kWave, kb, mbase, refa);
+        ja = map_window<false>(W, nrun, total, v0 + 2 * kWave, kb, mbase, refa, nextm);
         qa = load_galaxy(pos4, ja);
         step(qb, refb, jb, v0 + kWave);
       }
@@ -683,8 +717,8 @@ struct PairKernel {
       V ent;
       int jj = 0;
       if (lane < cnt) {
-        ent = W.ring[(head + lane) & (kRing - 1)];
-        if constexpr (SPILL) jj = W.ring_j[(head + lane) & (kRing - 1)];
+        ent = W.ring[lane];
+        if constexpr (SPILL) jj = W.ring_j[lane];
       } else {
         ent.x = Real(0);
         ent.y = Real(0);
