@@ -651,9 +651,10 @@ struct PairKernel {
           d[1] = dy;
           d[2] = dz;
           // no short circuit: no branches; lanes past the end hold NaN and
-          // fail both tests
+          // fail both tests.  The mask from the two compares' own lane masks
+          // (a ballot of their conjunction would first materialise it)
           acc = (r2 > lo2) & (r2 < hi2);
-          m = ballot(acc);
+          m = ballot(r2 > lo2) & ballot(r2 < hi2);
         } else {
           double r2;
           const int bin = P.bin64.classify(q, P.p, d, r2);
