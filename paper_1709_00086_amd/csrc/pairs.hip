@@ -73,6 +73,7 @@ namespace {
 constexpr int kWavesPerBlock = 4;
 constexpr int kMaxRuns = 4 * kWave;  // runs of one chunk of 64 rows (<= 4 per row)
 constexpr int kRing = 2 * kWave;     // accepted pairs waiting for a full wave
+constexpr int kAdjStripes = 16;      // interleaved stripes of an XCD's share (adjoint)
 // Run-start marks: one bit per virtual candidate index, for a span of
 // kMarkSpan candidates of the run table at a time (64 windows).
 constexpr int kMarkSpan = 64 * kWave;
@@ -946,7 +947,17 @@ struct PairKernel {
         if (lane == 0) t = atomicAdd(a.queue + x * kQueueStride, 1);
         t = uniform_int(__shfl(t, 0));
         if (lo + t < hi) {
-          qi = lo + t;
+          long long tt = t;
+          if constexpr (ADJOINT) {
+            // the adjoint hands out its share in kAdjStripes interleaved
+            // stripes: the waves of an XCD then work on primaries in
+            // kAdjStripes places at once, and their atomic adds into the
+            // secondaries' gradient meet on the same cache lines far less
+            // often than when all of them work on neighbouring primaries
+            const long long q = (hi - lo) / kAdjStripes;
+            if (tt < kAdjStripes * q) tt = (tt % kAdjStripes) * q + tt / kAdjStripes;
+          }
+          qi = lo + tt;
           found = true;
           break;
         }
@@ -996,7 +1007,8 @@ struct PairKernel {
       if constexpr (ADJOINT) w_prim = a.wsort[slot];
       if constexpr (kSpinT) primary_term(a, row, slot);
 
-      for (int b = 0; b < nb; ++b) {
+      for (int bb = 0; bb < nb; ++bb) {
+        const int b = uniform_int(bb);  // in a scalar register throughout the shell
         // annulus of shell b, widened by the search margin on both sides
         const double r0 = uniform_double(fmax(0.0, b * a.rmax / nb - margin));
         const double r1 =
