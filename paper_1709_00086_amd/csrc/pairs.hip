@@ -627,6 +627,13 @@ struct PairKernel {
     }
     int cnt = 0;
     unsigned accepted = 0;
+    // Wave priority: the search (run tables, window mapping, binning) is a
+    // chain of dependent LDS reads, position loads and compares, the
+    // accumulation independent arithmetic; a search at priority 1 over
+    // accumulations at 0 issues first when both are ready on a SIMD, and
+    // its next loads start sooner (the adjoint also raises the mapping and
+    // load issue to 2 over its binning).
+    __builtin_amdgcn_s_setprio(1);
     for (int rb = 0; rb < nrows; rb += kWave) {
       int total = 0;
       const int nrun = build_runs(a, cs, P, r0sq, r1sq, c0, nyr, inv_nyr, rb, nrows, W, total);
@@ -691,7 +698,9 @@ struct PairKernel {
             W.ring_j[lane] = W.ring_j[kWave + lane];
           }
           W.ring[lane] = rest;
+          __builtin_amdgcn_s_setprio(0);
           consume(ent, jj, true);
+          __builtin_amdgcn_s_setprio(1);
           cnt -= kWave;
         }
       };
@@ -705,15 +714,20 @@ struct PairKernel {
       int ja = map_window<false>(W, nrun, total, 0, kb, mbase, refa, nextm);
       V qa = load_galaxy(pos4, ja);
       for (int v0 = 0; v0 < total; v0 += 2 * kWave) {
+        if constexpr (ADJOINT) __builtin_amdgcn_s_setprio(2);
         const int jb = map_window<true>(W, nrun, total, v0 + kWave, kb, mbase, refb, nextm);
         const V qb = load_galaxy(pos4, jb);
+        if constexpr (ADJOINT) __builtin_amdgcn_s_setprio(1);
         step(qa, refa, ja, v0);
+        if constexpr (ADJOINT) __builtin_amdgcn_s_setprio(2);
         ja = map_window<false>(W, nrun, total, v0 + 2 * kWave, kb, mbase, refa, nextm);
         qa = load_galaxy(pos4, ja);
+        if constexpr (ADJOINT) __builtin_amdgcn_s_setprio(1);
         step(qb, refb, jb, v0 + kWave);
       }
       wave_lds_fence();
     }
+    __builtin_amdgcn_s_setprio(0);
     if (cnt > 0) {
       wave_lds_fence();
       V ent;
