@@ -91,7 +91,8 @@ __global__ void k_build_mh(const double* __restrict__ gz, AdjDims d, double* __r
 
 // H rows = X rows times M_H^T, per m, on FP64 MFMA.  One workgroup per
 // (64 primaries, 64 output columns of one m): each step stages a 64 x 16 slice
-// of X and a 16 x 64 slice of M_H^T in LDS, and each wave accumulates a 32 x 32
+// of X and a 16 x 64 slice of M_H^T in LDS (two stages, the next slice loaded
+// during the current one's MFMAs), and each wave accumulates a 32 x 32
 // quadrant as 2 x 2 MFMA tiles.  Lane l supplies A[i = l % 16][k = l / 16] and
 // B[k = l / 16][j = l % 16]; the FP64 result holds row g + 4 r (g = l / 16) in
 // register r.
@@ -128,8 +129,10 @@ __global__ __launch_bounds__(256) void k_h_gemm(const double* __restrict__ A,
                                                 const long long* __restrict__ nprim,
                                                 long long p_begin, long long p_count,
                                                 double* __restrict__ H) {
-  __shared__ double Xs[kHT][kHK + 1];   // odd row stride: rows spread over banks
-  __shared__ double Ms[kHK][kHT + 8];
+  // two stages: the next k slice's global loads are in flight (in
+  // registers) while the MFMAs work on the current one, one barrier a step
+  __shared__ double Xs[2][kHT][kHK + 1];   // odd row stride: rows spread over banks
+  __shared__ double Ms[2][kHK][kHT + 8];
   const int tid = threadIdx.x;
   const int lane = tid % kWave, wv = tid / kWave;
   const long long rows = min(p_count, (long long)(*nprim) - p_begin);
@@ -147,27 +150,44 @@ __global__ __launch_bounds__(256) void k_h_gemm(const double* __restrict__ A,
   const double* xp = A + (xrow < rows ? xrow : R0) * (long long)d.rowW + d.off[m];
   const int qi = (wv >> 1) * 32, qj = (wv & 1) * 32;
   const int li = lane % 16, g = lane / 16;
+  double xv[4], mv[4];
+  auto fetch = [&](int k0) {
+    for (int c = 0; c < 4; ++c) {
+      const int k = k0 + xk + c;
+      xv[c] = (xrow < rows && k < W) ? xp[k] : 0.0;
+      const int kk = k0 + mk, j = J0 + mc + c;
+      mv[c] = (kk < W && j < W) ? B[(long long)kk * W + j] : 0.0;
+    }
+  };
+  auto stage = [&](int s) {
+    for (int c = 0; c < 4; ++c) {
+      Xs[s][xr][xk + c] = xv[c];
+      Ms[s][mk][mc + c] = mv[c];
+    }
+  };
   double4_t acc[2][2];
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) acc[a][b] = double4_t{0.0, 0.0, 0.0, 0.0};
+  fetch(0);
+  stage(0);
+  __syncthreads();
+  int cur = 0;
   for (int k0 = 0; k0 < W; k0 += kHK) {
-    for (int c = 0; c < 4; ++c) {
-      const int k = k0 + xk + c;
-      Xs[xr][xk + c] = (xrow < rows && k < W) ? xp[k] : 0.0;
-      const int kk = k0 + mk, j = J0 + mc + c;
-      Ms[mk][mc + c] = (kk < W && j < W) ? B[(long long)kk * W + j] : 0.0;
-    }
-    __syncthreads();
+    const bool more = k0 + kHK < W;
+    if (more) fetch(k0 + kHK);
 #pragma unroll
     for (int k = 0; k < kHK; k += 4) {
       double xa[2], yb[2];
-      for (int a = 0; a < 2; ++a) xa[a] = Xs[qi + a * 16 + li][k + g];
-      for (int b = 0; b < 2; ++b) yb[b] = Ms[k + g][qj + b * 16 + li];
+      for (int a = 0; a < 2; ++a) xa[a] = Xs[cur][qi + a * 16 + li][k + g];
+      for (int b = 0; b < 2; ++b) yb[b] = Ms[cur][k + g][qj + b * 16 + li];
       for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[a], yb[b], acc[a][b], 0, 0, 0);
     }
+    // the other stage was last read before the previous barrier
+    if (more) stage(cur ^ 1);
     __syncthreads();
+    cur ^= 1;
   }
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b)
