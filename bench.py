@@ -361,7 +361,7 @@ def main():
     ap.add_argument("--build-probes", action="store_true",
                     help="compile bench_probes.hip (issue-rate and counter-calibration probes)")
     ap.add_argument("--probes", default=None, metavar="MODE",
-                    help="run the built probes: fma, accum, count or all (GPU)")
+                    help="run the built probes: fma, accum, count, mfma or all (GPU)")
     ap.add_argument("--summarise-rocprof", action="store_true",
                     help="summarise rocprofv3 CSV output instead of running (no GPU)")
     ap.add_argument("--counters", nargs="*", default=[])

@@ -10,6 +10,10 @@
 //           synthetic unit vector per lane per step) at 3 and 4 waves per SIMD.
 //   count   one launch that issues exactly 2^20 wave-level FP32 FMAs, to check
 //           what SQ_INSTS_VALU_FMA_F32 reads under rocprofv3.
+//   mfma    one launch per matrix instruction the library uses (FP32 16x16x4,
+//           FP64 16x16x4, BF16 16x16x32), each issuing a known number of
+//           wave-level MFMAs, to check the SQ_INSTS_VALU_MFMA_MOPS_* counters
+//           (512 flops a count) and time the instruction's issue rate.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -60,6 +64,67 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   float t = 0.f;
 #pragma unroll
   for (int i = 0; i < Acc::NT; ++i) t += a.acc[i];
+  out[blockIdx.x * blockDim.x + threadIdx.x] = t;
+}
+
+typedef float float4_v __attribute__((ext_vector_type(4)));
+typedef double double4_v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_v __attribute__((ext_vector_type(8)));
+
+// kMfmaChains independent accumulators per wave, kMfmaUnroll rounds per
+// iteration: iters x kMfmaUnroll x kMfmaChains wave-level MFMAs per wave.
+constexpr int kMfmaChains = 4;
+constexpr int kMfmaUnroll = 8;
+
+__global__ __launch_bounds__(256) void k_mfma_f32(float* out, int iters) {
+  const float a = 1.0f + threadIdx.x * 1e-6f, b = 0.5f - threadIdx.x * 1e-6f;
+  float4_v acc[kMfmaChains];
+  for (int c = 0; c < kMfmaChains; ++c) acc[c] = float4_v{0.f, 0.f, 0.f, 0.f};
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int r = 0; r < kMfmaUnroll; ++r)
+#pragma unroll
+      for (int c = 0; c < kMfmaChains; ++c)
+        acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[c], 0, 0, 0);
+  }
+  float t = 0.f;
+  for (int c = 0; c < kMfmaChains; ++c) t += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
+  out[blockIdx.x * blockDim.x + threadIdx.x] = t;
+}
+
+__global__ __launch_bounds__(256) void k_mfma_f64(float* out, int iters) {
+  const double a = 1.0 + threadIdx.x * 1e-6, b = 0.5 - threadIdx.x * 1e-6;
+  double4_v acc[kMfmaChains];
+  for (int c = 0; c < kMfmaChains; ++c) acc[c] = double4_v{0.0, 0.0, 0.0, 0.0};
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int r = 0; r < kMfmaUnroll; ++r)
+#pragma unroll
+      for (int c = 0; c < kMfmaChains; ++c)
+        acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
+  }
+  double t = 0.0;
+  for (int c = 0; c < kMfmaChains; ++c) t += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
+  out[blockIdx.x * blockDim.x + threadIdx.x] = float(t);
+}
+
+__global__ __launch_bounds__(256) void k_mfma_bf16(float* out, int iters) {
+  bf16x8_v a, b;
+  for (int q = 0; q < 8; ++q) {
+    a[q] = static_cast<__bf16>(1.0f + (threadIdx.x + q) * 1e-3f);
+    b[q] = static_cast<__bf16>(0.5f - (threadIdx.x + q) * 1e-3f);
+  }
+  float4_v acc[kMfmaChains];
+  for (int c = 0; c < kMfmaChains; ++c) acc[c] = float4_v{0.f, 0.f, 0.f, 0.f};
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int r = 0; r < kMfmaUnroll; ++r)
+#pragma unroll
+      for (int c = 0; c < kMfmaChains; ++c)
+        acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[c], 0, 0, 0);
+  }
+  float t = 0.f;
+  for (int c = 0; c < kMfmaChains; ++c) t += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
   out[blockIdx.x * blockDim.x + threadIdx.x] = t;
 }
 
@@ -127,6 +192,26 @@ void accum_rate(float* out, const char* name, int waves_per_simd, int valu_per_s
       name, waves_per_simd, ms, cyc, valu_per_step, cyc / valu_per_step);
 }
 
+// One launch of a matrix-instruction probe: 256 workgroups of 4 waves, each
+// wave iters x kMfmaUnroll x kMfmaChains MFMAs of flops_each flops.
+template <typename Kern>
+void mfma_count(float* out, Kern kern, const char* name, const char* counter, int flops_each) {
+  const int blocks = 256, iters = 2000;
+  const double ms = time_ms([&] {
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), 0, 0, out, iters);
+  });
+  if (ms < 0) return;
+  // the probe launches twice (warm-up and timed): per launch
+  const double insts = double(blocks) * 4 * iters * kMfmaUnroll * kMfmaChains;
+  std::printf(
+      "{\"probe\": \"mfma\", \"instruction\": \"%s\", \"counter\": \"%s\", "
+      "\"wave_mfma_per_launch\": %.0f, \"flops_each\": %d, "
+      "\"expected_counter_per_launch_at_512_flops\": %.0f, \"ms\": %.4f, "
+      "\"tflops\": %.2f}\n",
+      name, counter, insts, flops_each, insts * flops_each / 512.0, ms,
+      insts * flops_each / (ms * 1e-3) / 1e12);
+}
+
 }  // namespace
 
 int main(int argc, char** argv) {
@@ -150,6 +235,14 @@ int main(int argc, char** argv) {
     if (check(hipDeviceSynchronize(), "count launch"))
       std::printf("{\"probe\": \"count\", \"expected_wave_fma_f32\": %d}\n",
                   256 * 4 * (4 * 256 + 18));
+  }
+  if (all || !std::strcmp(mode, "mfma")) {
+    mfma_count(out, k_mfma_f32, "v_mfma_f32_16x16x4_f32", "SQ_INSTS_VALU_MFMA_MOPS_F32",
+               16 * 16 * 4 * 2);
+    mfma_count(out, k_mfma_f64, "v_mfma_f64_16x16x4_f64", "SQ_INSTS_VALU_MFMA_MOPS_F64",
+               16 * 16 * 4 * 2);
+    mfma_count(out, k_mfma_bf16, "v_mfma_f32_16x16x32_bf16", "SQ_INSTS_VALU_MFMA_MOPS_BF16",
+               16 * 16 * 32 * 2);
   }
   (void)hipFree(out);
   return 0;
