@@ -898,19 +898,21 @@ struct PairKernel {
         // atomics every kOutBuf / kWave waves: a wait for the candidate loads
         // then finds atomics outstanding (and has to wait for them, vmcnt
         // counting both) once per flush instead of after every wave of pairs.
+        // A full buffer is flushed before the next wave's polynomial, which
+        // then runs while the atomics complete.
         int nout = 0;
         got = search_shell<MINIMG, false>(
             a, W, pos4, P, b, r0, r1, [&](const V& e, int, bool valid) {
+              if (nout == kOutBuf) {
+                flush_terms(a, W, nout);
+                nout = 0;
+              }
               Real ux, uy, uz;
               unit<ROT>(P, e, ux, uy, uz);
               const float v = poly.eval(ux, uy, uz);
               W.out[nout + lane_here()] =
                   make_int2(valid ? unpack_index(e.w) : -1, __float_as_int(wp * v));
               nout += kWave;
-              if (nout == kOutBuf) {
-                flush_terms(a, W, nout);
-                nout = 0;
-              }
             });
         if (nout > 0) flush_terms(a, W, nout);
       } else {
